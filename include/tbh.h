@@ -1,0 +1,194 @@
+/*
+ * tbh.h -- C ABI of the MI355X tight-binding H.x / Lanczos / Schrodinger-Poisson
+ * library (libtbh.so).
+ *
+ * The method is the one of Lee, Ryu, Jiang and Klimeck, "Million Atom
+ * Electronic Structure and Device Calculations on Peta-Scale Computers":
+ * an empirical sp3s* / sp3d5s* nearest-neighbour tight-binding Hamiltonian
+ * with strain (Abstract; Sec. I), whose eigenstates near the band gap are
+ * found with a Lanczos solver (Sec. III-A, item 1; the benchmark unit of
+ * Sec. II-B is a fixed number of Lanczos iterations), inside a
+ * self-consistent Schrodinger-Poisson loop (Sec. III-A).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns a status code (TBH_OK = 0 or a negative TBH_E*);
+ *    nothing throws across the ABI.  tbh_last_error() returns a
+ *    thread-local message for the last failing call on this thread.
+ *  - On failure, outputs are left untouched unless the entry point says
+ *    otherwise (TBH_ENOCONV writes partial results).
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller (the library never frees caller memory).  Pointers documented as
+ *    "host" are ordinary host memory, read (or written) during the call only.
+ *  - Objects (tbh_ctx, tbh_ham, ...) own their internal device storage and
+ *    release it in the matching *_destroy call.
+ *  - All device work is enqueued on the context's HIP stream.  Calls that
+ *    return host values synchronise that stream before returning.
+ *  - Complex vectors and blocks are interleaved (re, im) pairs.
+ *  - Vector rows are atom-major, orbital-minor; with spin, the orbitals of
+ *    one atom are spin-major: row = atom*n_o + spin*n_base + orbital.
+ *  - Orbital order: sp3s* = [s, px, py, pz, s*];
+ *    sp3d5s* = [s, px, py, pz, dxy, dyz, dzx, dx2-y2, d3z2-r2, s*].
+ *  - Same inputs on the same GPU give bitwise identical outputs (all
+ *    reductions are fixed-order; no floating-point atomics).
+ *  - One context per host thread.
+ */
+#ifndef TBH_H
+#define TBH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TBH_OK        0
+#define TBH_EINVAL   -1   /* invalid argument (null pointer, bad size, bad geometry) */
+#define TBH_ENOMEM   -2   /* device or host allocation failed */
+#define TBH_EHIP     -3   /* a HIP runtime call failed */
+#define TBH_ENOCONV  -4   /* an iteration did not converge; partial results written */
+#define TBH_ESTATE   -5   /* object used in a wrong state */
+
+/* tight-binding models (Abstract; Sec. I) */
+#define TBH_SP3S     0    /* s, p(3), s*: 5 orbitals per atom and spin */
+#define TBH_SP3D5S   1    /* s, p(3), d(5), s*: 10 orbitals per atom and spin */
+
+/* storage precision of H and of the vectors it is applied to */
+#define TBH_F64      0
+#define TBH_F32      1
+
+typedef struct tbh_ctx tbh_ctx;
+typedef struct tbh_ham tbh_ham;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int tbh_version(void);
+
+/* Thread-local message of the last failing call; valid until the next call
+ * on this thread.  Never NULL. */
+const char* tbh_last_error(void);
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The stream must stay
+ * valid until tbh_ctx_destroy. */
+int tbh_ctx_create(int device, void* hip_stream, tbh_ctx** out);
+int tbh_ctx_destroy(tbh_ctx* ctx);
+/* Change the stream later calls enqueue on. */
+int tbh_ctx_set_stream(tbh_ctx* ctx, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Geometry and parameters (host memory, copied during the build call).
+ *
+ * Atoms sit on the diamond lattice in integer coordinates of a/4:
+ * sublattice A has all coordinates even with x+y+z = 0 (mod 4), sublattice
+ * B = A + (1,1,1).  Every coordinate must satisfy 0 <= q < box_q on every
+ * axis.  Bond slot b of an A atom points along d_b, with
+ * d_0=(1,1,1), d_1=(1,-1,-1), d_2=(-1,1,-1), d_3=(-1,-1,1); slot b of a B
+ * atom points along -d_b, so j = nbr(i,b) implies nbr(j,b) = i.  Periodic
+ * axes wrap modulo box_q; on hard-wall axes a bond leaving the box is
+ * dangling.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_atoms;
+    const int32_t* pos_q;     /* host [n_atoms][3], a/4 units */
+    const uint8_t* species;   /* host [n_atoms], each < n_species */
+    int32_t box_q[3];         /* box edge per axis, a/4 units (4 * cells) */
+    int32_t periodic[3];      /* 1 = periodic, 0 = hard wall */
+} tbh_geometry;
+
+/* Empirical tight-binding parameters (eV).
+ * onsite[s] = (E_s, E_p, E_d, E_s*) of species s (E_d unused for sp3s*).
+ * sk[a][b][14] = two-centre integrals of a bond between species a and b in
+ * the order ss_sigma, s*s*_sigma, ss*_sigma, sp_sigma, s*p_sigma, sd_sigma,
+ * s*d_sigma, pp_sigma, pp_pi, pd_sigma, pd_pi, dd_sigma, dd_pi, dd_delta
+ * (Slater & Koster two-centre form; the d-shell ones unused for sp3s*).
+ * The set must be symmetric (sk[a][b] == sk[b][a]).
+ * so_delta[s] = spin-orbit splitting Delta of the p shell, used when spin=1:
+ * on-site lambda L.S with lambda = 2 Delta / 3 (NULL = 0).
+ * passivation_eV: each dangling bond adds passivation_eV * |h><h| to the
+ * on-site block, h = (s + d.p)/2 the sp3 hybrid along the missing bond
+ * (0 = off). */
+typedef struct {
+    int32_t model;            /* TBH_SP3S or TBH_SP3D5S */
+    int32_t spin;             /* 0: no spin; 1: spin-major doubling + spin-orbit */
+    int32_t n_species;        /* 1..16 */
+    const double* onsite;     /* host [n_species][4] */
+    const double* sk;         /* host [n_species][n_species][14] */
+    const double* so_delta;   /* host [n_species] or NULL */
+    double passivation_eV;
+} tbh_params;
+
+typedef struct {
+    /* host [n_atoms][4] hopping scale per bond slot (strain), or NULL = 1.
+     * Only rows of A-sublattice atoms are read; the reverse direction of a
+     * bond uses its A atom's factor. */
+    const double* bond_scale;
+    /* host [n_atoms] on-site potential energy (eV) added to every orbital of
+     * the atom, or NULL = 0. */
+    const double* onsite_pot;
+    /* host [3] Bloch vector as fractions of the box reciprocal vectors; a
+     * bond that wraps by w boxes gets the phase exp(2 pi i k.w).  NULL =
+     * Gamma.  A non-zero k makes H complex. */
+    const double* kfrac;
+    int32_t prec;             /* TBH_F64 or TBH_F32 */
+    /* lanes of a wavefront that share one atom's rows (1..n_o, must divide
+     * n_o); 0 = choose automatically. */
+    int32_t lanes_per_atom;
+    /* TBH_F32 only: also keep an FP64 copy of H for residuals and
+     * Rayleigh-quotient refinement (tbh_apply_h_f64, tbh_lanczos_eigs). */
+    int32_t keep_f64;
+} tbh_build_opts;
+
+typedef struct {
+    int64_t n_atoms;
+    int64_t dim;              /* n_atoms * n_orb (complex elements if complex) */
+    int32_t n_orb;            /* orbitals per atom, spin included */
+    int32_t is_complex;
+    int32_t prec;
+    int32_t lanes_per_atom;
+    int32_t onsite_diagonal;  /* 1 if every on-site block is diagonal */
+    int32_t has_f64;          /* FP64 copy present */
+    int64_t n_dangling;       /* dangling bond slots */
+    int64_t stored_bytes;     /* device bytes of the packed H (main precision) */
+    int64_t hx_bytes;         /* algorithmic bytes of one H.x: packed H +
+                                 neighbour table + x once + y once */
+} tbh_ham_info;
+
+/* Pure host step of the build: neighbour table and the assembled FP64
+ * blocks, written to caller-owned host arrays.  No device is touched.
+ * nbr: [n][4] int32 (-1 = dangling); wrap: [n][4][3] int8;
+ * onsite: [n][n_o][n_o] and bonds: [n][4][n_o][n_o] as doubles, complex
+ * interleaved when H is complex (either may be NULL).  Bond block (i,b) is
+ * <i,row|H|nbr(i,b),col>; the block of a B atom is exactly the conjugate
+ * transpose of its partner's. */
+int tbh_build_blocks_host(const tbh_geometry* g, const tbh_params* p,
+                          const tbh_build_opts* o, int32_t* nbr, int8_t* wrap,
+                          double* onsite, double* bonds, int32_t* is_complex);
+
+/* Build H on the context's device: neighbour search, Slater-Koster bond
+ * blocks (strain, Bloch phase), on-site blocks (spin-orbit, passivation,
+ * potential), packed into the atom-ordered block layout the kernels stream.
+ * *out owns its device memory; release it with tbh_ham_destroy. */
+int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params* p,
+                          const tbh_build_opts* o, tbh_ham** out);
+int tbh_ham_destroy(tbh_ham* h);
+int tbh_ham_info_get(const tbh_ham* h, tbh_ham_info* out);
+/* Host copies of the neighbour table ([n][4]) and wraps ([n][4][3]). */
+int tbh_ham_neighbours(const tbh_ham* h, int32_t* nbr, int8_t* wrap);
+
+/* Replace the per-atom on-site potential (Schrodinger-Poisson update, Sec.
+ * III-A item 3): pot_dev is device [n_atoms] FP64 (eV), or NULL = 0.  The
+ * blocks are not rebuilt; H.x adds pot[i] * x_i. */
+int tbh_ham_set_potential(tbh_ham* h, const double* pot_dev);
+
+/* y = H x.  x, y: device, [dim] scalars of the ham's precision (complex
+ * interleaved) for nrhs = 1, or [dim][nrhs] (right-hand vectors fastest)
+ * for nrhs > 1.  x and y must not overlap. */
+int tbh_apply_h(tbh_ham* h, const void* x, void* y, int32_t nrhs);
+/* y = H x in FP64 with the FP64 copy (or the main copy for TBH_F64). */
+int tbh_apply_h_f64(tbh_ham* h, const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TBH_H */

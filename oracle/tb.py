@@ -388,3 +388,42 @@ def bulk_hk(model, spin, E, V, so_delta, k_cart):
     H[:n_o, n_o:] = HAB
     H[n_o:, :n_o] = HAB.conj().T
     return H
+
+
+def hx_rows(prob, atoms, x, nbr=None, wrap=None):
+    """Rows of y = H x belonging to the given atoms, computed atom by atom
+    from the definition (for spot checks at sizes where the full CSR matrix
+    is too large).  Returns [len(atoms), n_o] (complex if H is complex)."""
+    par = prob.params
+    model, spin = par["model"], par["spin"]
+    nb = n_base_orbitals(model)
+    n_o = nb * (2 if spin else 1)
+    if nbr is None:
+        nbr, wrap = find_neighbours(prob.pos_q, prob.box_q, prob.periodic)
+    sub = sublattice(prob.pos_q)
+    spc = np.asarray(prob.species, dtype=np.int64)
+    kf = np.zeros(3) if prob.kfrac is None else np.asarray(prob.kfrac, dtype=np.float64)
+    cplx = bool(spin) or bool(np.any(kf != 0))
+    X = np.asarray(x).reshape(-1, n_o)
+    out = np.zeros((len(atoms), n_o), dtype=complex if cplx else float)
+    for r, i in enumerate(atoms):
+        sgn = 1 if sub[i] == 0 else -1
+        dirs = [sgn * SLOT_DIRS[b] for b in range(4) if nbr[i, b] < 0]
+        U = 0.0 if prob.onsite_pot is None else prob.onsite_pot[i]
+        D = onsite_block(model, spin, par["onsite"][spc[i]], U, par["so_delta"][spc[i]],
+                         dirs, par["passivation_eV"])
+        acc = D @ X[i]
+        for b in range(4):
+            j = nbr[i, b]
+            if j < 0:
+                continue
+            B = sk_block(model, par["sk"][spc[i]][spc[j]], sgn * SLOT_DIRS[b])
+            if prob.bond_scale is not None:
+                B = B * prob.bond_scale[i if sub[i] == 0 else j, b]
+            if spin:
+                B = np.kron(np.eye(2), B)
+            if cplx:
+                B = B * np.exp(2j * np.pi * np.dot(kf, wrap[i, b]))
+            acc = acc + B @ X[j]
+        out[r] = acc
+    return out

@@ -1,0 +1,308 @@
+"""Python binding of libtbh.so: MI355X tight-binding H.x, Lanczos and
+Schrodinger-Poisson.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Device vectors are torch tensors on a HIP device (PyTorch provides device
+memory and streams); host inputs are numpy arrays.  The binding fails loudly
+when the library has not been built -- there is no CPU fallback.
+
+The function names are those of the C ABI (include/tbh.h) without the
+``tbh_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtbh.so")
+
+TBH_OK, TBH_EINVAL, TBH_ENOMEM, TBH_EHIP, TBH_ENOCONV, TBH_ESTATE = 0, -1, -2, -3, -4, -5
+TBH_SP3S, TBH_SP3D5S = 0, 1
+TBH_F64, TBH_F32 = 0, 1
+
+
+class TBHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tbh error {code}: {msg}")
+        self.code = code
+
+
+class tbh_geometry(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("pos_q", C.POINTER(C.c_int32)),
+                ("species", C.POINTER(C.c_uint8)), ("box_q", C.c_int32 * 3),
+                ("periodic", C.c_int32 * 3)]
+
+
+class tbh_params(C.Structure):
+    _fields_ = [("model", C.c_int32), ("spin", C.c_int32), ("n_species", C.c_int32),
+                ("onsite", C.POINTER(C.c_double)), ("sk", C.POINTER(C.c_double)),
+                ("so_delta", C.POINTER(C.c_double)), ("passivation_eV", C.c_double)]
+
+
+class tbh_build_opts(C.Structure):
+    _fields_ = [("bond_scale", C.POINTER(C.c_double)), ("onsite_pot", C.POINTER(C.c_double)),
+                ("kfrac", C.POINTER(C.c_double)), ("prec", C.c_int32),
+                ("lanes_per_atom", C.c_int32), ("keep_f64", C.c_int32)]
+
+
+class tbh_ham_info(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("dim", C.c_int64), ("n_orb", C.c_int32),
+                ("is_complex", C.c_int32), ("prec", C.c_int32), ("lanes_per_atom", C.c_int32),
+                ("onsite_diagonal", C.c_int32), ("has_f64", C.c_int32),
+                ("n_dangling", C.c_int64), ("stored_bytes", C.c_int64), ("hx_bytes", C.c_int64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_SIGS = [
+    ("tbh_version", C.c_int, []),
+    ("tbh_last_error", C.c_char_p, []),
+    ("tbh_ctx_create", C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("tbh_ctx_destroy", C.c_int, [C.c_void_p]),
+    ("tbh_ctx_set_stream", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_build_blocks_host", C.c_int, [C.POINTER(tbh_geometry), C.POINTER(tbh_params),
+                                        C.POINTER(tbh_build_opts), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    ("tbh_build_hamiltonian", C.c_int, [C.c_void_p, C.POINTER(tbh_geometry), C.POINTER(tbh_params),
+                                        C.POINTER(tbh_build_opts), C.POINTER(C.c_void_p)]),
+    ("tbh_ham_destroy", C.c_int, [C.c_void_p]),
+    ("tbh_ham_info_get", C.c_int, [C.c_void_p, C.POINTER(tbh_ham_info)]),
+    ("tbh_ham_neighbours", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("tbh_ham_set_potential", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_apply_h", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("tbh_apply_h_f64", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+]
+
+
+def lib():
+    """Load libtbh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1003_4570_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [s[0] for s in _SIGS]
+
+
+def _check(rc):
+    if rc != TBH_OK:
+        raise TBHError(rc, lib().tbh_last_error().decode())
+
+
+def _dptr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a, ctype):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ctype))
+
+
+def last_error() -> str:
+    return lib().tbh_last_error().decode()
+
+
+def version() -> int:
+    return lib().tbh_version()
+
+
+class _Inputs:
+    """Host arrays kept alive for the duration of one call."""
+
+    def __init__(self, pos_q, species, box_q, periodic, model, spin, onsite, sk,
+                 so_delta=None, passivation_eV=0.0, bond_scale=None, onsite_pot=None,
+                 kfrac=None, prec=TBH_F32, lanes_per_atom=0, keep_f64=False, n_species=None):
+        self.pos = _dptr(pos_q, np.int32).reshape(-1, 3)
+        self.spc = _dptr(species, np.uint8).ravel()
+        self.onsite = _dptr(onsite, np.float64)
+        self.sk = _dptr(sk, np.float64)
+        ns = int(self.onsite.shape[0]) if n_species is None else int(n_species)
+        self.so = None if so_delta is None else _dptr(so_delta, np.float64)
+        self.bs = None if bond_scale is None else _dptr(bond_scale, np.float64)
+        self.pot = None if onsite_pot is None else _dptr(onsite_pot, np.float64)
+        self.kf = None if kfrac is None else _dptr(kfrac, np.float64)
+        if isinstance(prec, str):
+            prec = TBH_F64 if prec == "f64" else TBH_F32
+        self.g = tbh_geometry(self.pos.shape[0], _p(self.pos, C.c_int32), _p(self.spc, C.c_uint8),
+                              (C.c_int32 * 3)(*[int(b) for b in box_q]),
+                              (C.c_int32 * 3)(*[int(b) for b in periodic]))
+        self.par = tbh_params(int(model), int(spin), ns, _p(self.onsite, C.c_double),
+                              _p(self.sk, C.c_double), _p(self.so, C.c_double), float(passivation_eV))
+        self.opt = tbh_build_opts(_p(self.bs, C.c_double), _p(self.pot, C.c_double),
+                                  _p(self.kf, C.c_double), int(prec), int(lanes_per_atom),
+                                  int(bool(keep_f64)))
+        self.n = self.pos.shape[0]
+        self.n_o = (5 if int(model) == TBH_SP3S else 10) * (2 if spin else 1)
+
+
+def problem_args(prob, prec=None, **kw):
+    """Keyword arguments of build_hamiltonian for a workloads.Problem-like
+    object (attributes pos_q, species, box_q, periodic, params, bond_scale,
+    onsite_pot, kfrac, prec)."""
+    par = prob.params
+    d = dict(pos_q=prob.pos_q, species=prob.species, box_q=prob.box_q, periodic=prob.periodic,
+             model=par["model"], spin=par["spin"], onsite=par["onsite"], sk=par["sk"],
+             so_delta=par["so_delta"], passivation_eV=par["passivation_eV"],
+             bond_scale=prob.bond_scale, onsite_pot=prob.onsite_pot, kfrac=prob.kfrac,
+             prec=prob.prec if prec is None else prec)
+    d.update(kw)
+    return d
+
+
+def build_blocks_host(**kw):
+    """Host-only build step: (nbr [n,4], wrap [n,4,3], onsite, bonds, complex).
+    onsite [n, n_o, n_o] and bonds [n, 4, n_o, n_o] are float64 or complex128."""
+    a = _Inputs(**kw)
+    n, no = a.n, a.n_o
+    nbr = np.empty((n, 4), np.int32)
+    wrap = np.empty((n, 4, 3), np.int8)
+    isc = C.c_int32(0)
+    _check(lib().tbh_build_blocks_host(C.byref(a.g), C.byref(a.par), C.byref(a.opt),
+                                       nbr.ctypes.data, wrap.ctypes.data, None, None, C.byref(isc)))
+    cs = 2 if isc.value else 1
+    on = np.empty(n * no * no * cs)
+    bd = np.empty(n * 4 * no * no * cs)
+    _check(lib().tbh_build_blocks_host(C.byref(a.g), C.byref(a.par), C.byref(a.opt),
+                                       None, None, on.ctypes.data, bd.ctypes.data, None))
+    if cs == 2:
+        on = on.view(np.complex128)
+        bd = bd.view(np.complex128)
+    return nbr, wrap, on.reshape(n, no, no), bd.reshape(n, 4, no, no), bool(isc.value)
+
+
+class Context:
+    """A library context on one HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().tbh_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tbh_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """A device Hamiltonian built by tbh_build_hamiltonian."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.h = handle
+        info = tbh_ham_info()
+        _check(lib().tbh_ham_info_get(self.h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in tbh_ham_info._fields_}
+
+    @property
+    def dim(self):
+        return self.info["dim"]
+
+    @property
+    def is_complex(self):
+        return bool(self.info["is_complex"])
+
+    @property
+    def prec(self):
+        return self.info["prec"]
+
+    def torch_dtype(self, f64=False):
+        import torch
+        if self.prec == TBH_F64 or f64:
+            return torch.complex128 if self.is_complex else torch.float64
+        return torch.complex64 if self.is_complex else torch.float32
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tbh_ham_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_hamiltonian(ctx: Context, **kw) -> Hamiltonian:
+    """Build H on the context's device (see problem_args for the keywords)."""
+    a = _Inputs(**kw)
+    h = C.c_void_p()
+    _check(lib().tbh_build_hamiltonian(ctx.h, C.byref(a.g), C.byref(a.par), C.byref(a.opt), C.byref(h)))
+    return Hamiltonian(ctx, h)
+
+
+def ham_neighbours(ham: Hamiltonian):
+    n = ham.info["n_atoms"]
+    nbr = np.empty((n, 4), np.int32)
+    wrap = np.empty((n, 4, 3), np.int8)
+    _check(lib().tbh_ham_neighbours(ham.h, nbr.ctypes.data, wrap.ctypes.data))
+    return nbr, wrap
+
+
+def _check_vec(ham, t, f64=False):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("device vectors must be torch tensors on a HIP device")
+    if t.dtype != ham.torch_dtype(f64):
+        raise TypeError(f"expected dtype {ham.torch_dtype(f64)}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("vectors must be contiguous")
+
+
+def ham_set_potential(ham: Hamiltonian, pot):
+    """pot: float64 device tensor [n_atoms] (eV) or None."""
+    if pot is None:
+        _check(lib().tbh_ham_set_potential(ham.h, None))
+        return
+    import torch
+    assert pot.dtype == torch.float64 and pot.is_cuda and pot.numel() == ham.info["n_atoms"]
+    _check(lib().tbh_ham_set_potential(ham.h, C.c_void_p(pot.data_ptr())))
+
+
+def apply_h(ham: Hamiltonian, x, y=None):
+    """y = H x on the device (x, y: [dim] tensors of the ham's dtype)."""
+    import torch
+    _check_vec(ham, x)
+    if y is None:
+        y = torch.empty_like(x)
+    _check_vec(ham, y)
+    if x.numel() != ham.dim or y.numel() != ham.dim:
+        raise ValueError("vector length must equal dim")
+    _check(lib().tbh_apply_h(ham.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), 1))
+    return y
+
+
+def apply_h_f64(ham: Hamiltonian, x, y=None):
+    """y = H x in FP64 with the FP64 copy of H."""
+    import torch
+    _check_vec(ham, x, f64=True)
+    if y is None:
+        y = torch.empty_like(x)
+    _check_vec(ham, y, f64=True)
+    _check(lib().tbh_apply_h_f64(ham.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+    return y

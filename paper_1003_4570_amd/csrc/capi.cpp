@@ -1,0 +1,268 @@
+// C ABI: contexts, Hamiltonian build and H.x entry points.
+#include <cstring>
+#include <memory>
+
+#include "tbh_internal.h"
+
+namespace {
+thread_local std::string g_err;
+
+template <typename F>
+int guard(F&& f) {
+    try {
+        f();
+        g_err.clear();
+        return TBH_OK;
+    } catch (const tbh::Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return TBH_ENOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return TBH_EINVAL;
+    }
+}
+}  // namespace
+
+struct tbh_ctx : tbh::Ctx {};
+struct tbh_ham : tbh::Ham {};
+
+namespace tbh {
+
+int64_t Ham::hx_bytes() const {
+    const int64_t vec = dim * (cplx_h ? 2 : 1) * (prec == TBH_F64 ? 8 : 4);
+    return lay.bytes + n * 4 * 4 + 2 * vec + (has_pot ? n * 8 : 0);
+}
+
+namespace {
+
+int choose_rows(int n_o, bool cplx_h, int prec, int64_t n_atoms, int lanes) {
+    if (lanes > 0) {
+        TBH_REQUIRE(lanes <= n_o && n_o % lanes == 0, "lanes_per_atom must divide the orbital count");
+        const int R = n_o / lanes;
+        TBH_REQUIRE(hx_shape_supported(n_o, cplx_h, R),
+                    "no kernel for lanes_per_atom=" + std::to_string(lanes));
+        return R;
+    }
+    // fewest lanes per atom (least gather redundancy) whose launch still has
+    // enough wavefronts to fill 256 CUs many times over; otherwise the most
+    // parallel shape available
+    const int K = prec == TBH_F64 ? 2 : 4;
+    int last = 0;
+    for (int R : {20, 10, 5, 4, 2, 1}) {
+        if (R > n_o || n_o % R || !hx_shape_supported(n_o, cplx_h, R)) continue;
+        last = R;
+        const int atoms_per_tile = 64 / (n_o / R);
+        const int64_t tiles = (n_atoms + atoms_per_tile - 1) / atoms_per_tile;
+        const bool aligned = (R * n_o * (cplx_h ? 2 : 1)) % K == 0;
+        if (aligned && tiles >= 4096) return R;
+    }
+    TBH_REQUIRE(last > 0, "no H.x kernel shape for this orbital count");
+    return last;
+}
+
+}  // namespace
+}  // namespace tbh
+
+extern "C" {
+
+int tbh_version(void) { return 100; }
+
+const char* tbh_last_error(void) { return g_err.c_str(); }
+
+int tbh_ctx_create(int device, void* stream, tbh_ctx** out) {
+    return guard([&] {
+        TBH_REQUIRE(out, "null output pointer");
+        int n = 0;
+        TBH_HIP(hipGetDeviceCount(&n));
+        TBH_REQUIRE(device >= 0 && device < n, "device index out of range");
+        TBH_HIP(hipSetDevice(device));
+        auto c = std::make_unique<tbh_ctx>();
+        c->device = device;
+        c->stream = static_cast<hipStream_t>(stream);
+        *out = c.release();
+    });
+}
+
+int tbh_ctx_destroy(tbh_ctx* c) {
+    return guard([&] {
+        if (!c) return;
+        (void)hipSetDevice(c->device);
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+        delete c;
+    });
+}
+
+int tbh_ctx_set_stream(tbh_ctx* c, void* stream) {
+    return guard([&] {
+        TBH_REQUIRE(c, "null context");
+        c->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+int tbh_build_blocks_host(const tbh_geometry* g, const tbh_params* p, const tbh_build_opts* o,
+                          int32_t* nbr, int8_t* wrap, double* onsite, double* bonds,
+                          int32_t* is_complex) {
+    return guard([&] {
+        tbh::HostModel M;
+        tbh::host_prepare(g, p, o, M);
+        if (nbr) std::memcpy(nbr, M.nbr.data(), M.nbr.size() * 4);
+        if (wrap) std::memcpy(wrap, M.wrap.data(), M.wrap.size());
+        if (is_complex) *is_complex = M.cplx_h;
+        if (!onsite && !bonds) return;
+        const int no = M.n_o;
+        std::vector<tbh::cplx> D(no * no), B(4 * no * no);
+        const int cs = M.cplx_h ? 2 : 1;
+        for (int64_t i = 0; i < M.n; ++i) {
+            tbh::host_atom_blocks(M, i, D.data(), B.data());
+            if (onsite)
+                for (int k = 0; k < no * no; ++k) {
+                    onsite[(i * no * no + k) * cs] = D[k].real();
+                    if (cs == 2) onsite[(i * no * no + k) * cs + 1] = D[k].imag();
+                }
+            if (bonds)
+                for (int k = 0; k < 4 * no * no; ++k) {
+                    bonds[(i * 4 * no * no + k) * cs] = B[k].real();
+                    if (cs == 2) bonds[(i * 4 * no * no + k) * cs + 1] = B[k].imag();
+                }
+        }
+    });
+}
+
+int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params* p,
+                          const tbh_build_opts* o, tbh_ham** out) {
+    return guard([&] {
+        TBH_REQUIRE(ctx && out, "null context or output pointer");
+        TBH_HIP(hipSetDevice(ctx->device));
+        tbh::HostModel M;
+        tbh::host_prepare(g, p, o, M);
+        auto h = std::make_unique<tbh_ham>();
+        h->ctx = ctx;
+        h->n = M.n;
+        h->n_o = M.n_o;
+        h->n_base = M.n_base;
+        h->dim = M.n * M.n_o;
+        h->cplx_h = M.cplx_h;
+        h->spin = M.spin;
+        h->prec = o->prec;
+        h->n_dangling = M.n_dangling;
+        h->nbr_h = M.nbr;
+        h->wrap_h = M.wrap;
+        // diagonal on-site blocks need no spin-orbit, no passivation
+        h->diag = !M.spin && !(M.par.passivation_eV != 0.0 && M.n_dangling > 0);
+        const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);
+        h->lay = tbh::make_layout(M.n, M.n_o, M.cplx_h, o->prec, R, h->diag);
+        {
+            std::vector<char> host(size_t(h->lay.bytes));
+            tbh::pack_layout(M, h->lay, h->diag, host.data());
+            h->blocks.alloc(host.size());
+            TBH_HIP(hipMemcpy(h->blocks.p, host.data(), host.size(), hipMemcpyHostToDevice));
+        }
+        if (o->prec == TBH_F32 && o->keep_f64) {
+            h->lay64 = tbh::make_layout(M.n, M.n_o, M.cplx_h, TBH_F64, R, h->diag);
+            std::vector<char> host(size_t(h->lay64.bytes));
+            tbh::pack_layout(M, h->lay64, h->diag, host.data());
+            h->blocks64.alloc(host.size());
+            TBH_HIP(hipMemcpy(h->blocks64.p, host.data(), host.size(), hipMemcpyHostToDevice));
+            h->has_f64 = true;
+        } else if (o->prec == TBH_F64) {
+            h->has_f64 = true;
+        }
+        h->nbr_d.alloc(M.nbr.size() * 4);
+        TBH_HIP(hipMemcpy(h->nbr_d.p, M.nbr.data(), M.nbr.size() * 4, hipMemcpyHostToDevice));
+        *out = h.release();
+    });
+}
+
+int tbh_ham_destroy(tbh_ham* h) {
+    return guard([&] {
+        if (!h) return;
+        (void)hipSetDevice(h->ctx->device);
+        if (h->ctx->stream) (void)hipStreamSynchronize(h->ctx->stream);
+        else (void)hipDeviceSynchronize();
+        delete h;
+    });
+}
+
+int tbh_ham_info_get(const tbh_ham* h, tbh_ham_info* out) {
+    return guard([&] {
+        TBH_REQUIRE(h && out, "null argument");
+        out->n_atoms = h->n;
+        out->dim = h->dim;
+        out->n_orb = h->n_o;
+        out->is_complex = h->cplx_h;
+        out->prec = h->prec;
+        out->lanes_per_atom = h->lay.G;
+        out->onsite_diagonal = h->diag;
+        out->has_f64 = h->has_f64;
+        out->n_dangling = h->n_dangling;
+        out->stored_bytes = h->lay.bytes;
+        out->hx_bytes = h->hx_bytes();
+    });
+}
+
+int tbh_ham_neighbours(const tbh_ham* h, int32_t* nbr, int8_t* wrap) {
+    return guard([&] {
+        TBH_REQUIRE(h, "null ham");
+        if (nbr) std::memcpy(nbr, h->nbr_h.data(), h->nbr_h.size() * 4);
+        if (wrap) std::memcpy(wrap, h->wrap_h.data(), h->wrap_h.size());
+    });
+}
+
+int tbh_ham_set_potential(tbh_ham* h, const double* pot_dev) {
+    return guard([&] {
+        TBH_REQUIRE(h, "null ham");
+        TBH_HIP(hipSetDevice(h->ctx->device));
+        if (!pot_dev) {
+            h->has_pot = false;
+            return;
+        }
+        h->pot_d.alloc(size_t(h->n) * 8);
+        TBH_HIP(hipMemcpyAsync(h->pot_d.p, pot_dev, size_t(h->n) * 8, hipMemcpyDeviceToDevice,
+                               h->ctx->stream));
+        h->has_pot = true;
+    });
+}
+
+int tbh_apply_h(tbh_ham* h, const void* x, void* y, int32_t nrhs) {
+    return guard([&] {
+        TBH_REQUIRE(h && x && y, "null argument");
+        TBH_REQUIRE(nrhs == 1, "tbh_apply_h: nrhs must be 1 (multi-vector form: tbh_apply_h_multi)");
+        TBH_REQUIRE(x != y, "x and y must not overlap");
+        TBH_REQUIRE((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 16 == 0,
+                    "x and y must be 16-byte aligned");
+        TBH_HIP(hipSetDevice(h->ctx->device));
+        tbh::HxArgs a;
+        a.blocks = h->blocks.p;
+        a.nbr = h->nbr_d.as<int32_t>();
+        a.x = x;
+        a.y = y;
+        a.pot = h->has_pot ? h->pot_d.as<double>() : nullptr;
+        a.n_atoms = h->n;
+        tbh::hx_launch(h->lay, h->prec == TBH_F64, a, h->ctx->stream);
+    });
+}
+
+int tbh_apply_h_f64(tbh_ham* h, const double* x, double* y) {
+    return guard([&] {
+        TBH_REQUIRE(h && x && y, "null argument");
+        TBH_REQUIRE(h->has_f64, "no FP64 copy of H (build with keep_f64=1)");
+        TBH_REQUIRE(x != y, "x and y must not overlap");
+        TBH_REQUIRE((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 16 == 0,
+                    "x and y must be 16-byte aligned");
+        TBH_HIP(hipSetDevice(h->ctx->device));
+        tbh::HxArgs a;
+        const bool main64 = h->prec == TBH_F64;
+        a.blocks = main64 ? h->blocks.p : h->blocks64.p;
+        a.nbr = h->nbr_d.as<int32_t>();
+        a.x = x;
+        a.y = y;
+        a.pot = h->has_pot ? h->pot_d.as<double>() : nullptr;
+        a.n_atoms = h->n;
+        tbh::hx_launch(main64 ? h->lay : h->lay64, true, a, h->ctx->stream);
+    });
+}
+
+}  // extern "C"

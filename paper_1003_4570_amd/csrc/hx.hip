@@ -1,0 +1,319 @@
+// Block H.x for gfx950: y = D_i x_i + sum_b B_ib x_nbr(i,b) (+ U_i x_i).
+//
+// The Hamiltonian is the nearest-neighbour tight-binding matrix of the
+// paper (Abstract; Sec. I); its application to a vector is the unit of cost
+// of every Lanczos iteration the paper benchmarks (Sec. II-B).  On one GPU
+// the operation is HBM-bound (about 0.5 flop per byte), so the kernel is
+// organised around streaming the packed blocks once at full bandwidth:
+//
+//  * one 64-lane wavefront per tile of atoms; each lane owns R rows of one
+//    atom and streams its private, chunk-interleaved segment of the block
+//    array with 16-byte non-temporal loads (every wavefront load is one
+//    contiguous L*16-byte read);
+//  * neighbour vector slices are gathered through the cache hierarchy (the
+//    whole x of a million-atom problem, 42 MB in FP32, stays in the 256 MB
+//    Infinity Cache, and neighbouring atoms share lines in L2);
+//  * workgroups are mapped XCD-contiguously, so the tiles one XCD processes
+//    are spatial neighbours and share their gathered x lines in that XCD's L2;
+//  * the Lanczos epilogue fuses y -= beta * x_prev and the FP64 partial sums
+//    of Re(x^H y) and |y|^2 (wavefront shuffles, then one LDS step per
+//    workgroup; no atomics, fixed order).
+#include "tbh_internal.h"
+
+namespace tbh {
+
+namespace {
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblk) {
+    const int64_t xcd = bid % 8, idx = bid / 8, q = nblk / 8, r = nblk % 8;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Load n contiguous scalars starting at p (element offset off) with the
+// widest aligned vector the static row size allows.
+template <typename T, int N, int ROWBYTES>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, T (&out)[N]) {
+    if constexpr (ROWBYTES % 16 == 0 && (N * sizeof(T)) % 16 == 0) {
+        typedef typename Vec16<T>::type V;
+        constexpr int K = 16 / sizeof(T);
+#pragma unroll
+        for (int c = 0; c < N / K; ++c) {
+            V v = reinterpret_cast<const V*>(p)[c];
+#pragma unroll
+            for (int e = 0; e < K; ++e) out[c * K + e] = v[e];
+        }
+    } else if constexpr (sizeof(T) == 4 && ROWBYTES % 8 == 0 && N % 2 == 0) {
+        typedef float V2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int c = 0; c < N / 2; ++c) {
+            V2 v = reinterpret_cast<const V2*>(p)[c];
+            out[2 * c] = v[0];
+            out[2 * c + 1] = v[1];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c) out[c] = p[c];
+    }
+}
+
+template <typename T, int N, int ROWBYTES>
+__device__ __forceinline__ void store_row(T* __restrict__ p, const T (&in)[N]) {
+    if constexpr (ROWBYTES % 16 == 0 && (N * sizeof(T)) % 16 == 0) {
+        typedef typename Vec16<T>::type V;
+        constexpr int K = 16 / sizeof(T);
+#pragma unroll
+        for (int c = 0; c < N / K; ++c) {
+            V v;
+#pragma unroll
+            for (int e = 0; e < K; ++e) v[e] = in[c * K + e];
+            reinterpret_cast<V*>(p)[c] = v;
+        }
+    } else if constexpr (sizeof(T) == 4 && ROWBYTES % 8 == 0 && N % 2 == 0) {
+        typedef float V2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int c = 0; c < N / 2; ++c) {
+            V2 v;
+            v[0] = in[2 * c];
+            v[1] = in[2 * c + 1];
+            reinterpret_cast<V2*>(p)[c] = v;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c) p[c] = in[c];
+    }
+}
+
+// acc[R rows] += M[R x NO] * xv[NO] where M is streamed chunk by chunk from
+// the lane's segment (CH chunks of K scalars, row-major, padded at the end).
+template <typename T, bool CPLX, int NO, int R>
+__device__ __forceinline__ void stream_rows(const typename Vec16<T>::type* __restrict__ src, int L,
+                                            const T (&xv)[NO * (CPLX ? 2 : 1)],
+                                            T (&acc)[R * (CPLX ? 2 : 1)]) {
+    constexpr int CS = CPLX ? 2 : 1;
+    constexpr int K = 16 / sizeof(T);
+    constexpr int S = R * NO * CS;
+    constexpr int CH = (S + K - 1) / K;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const typename Vec16<T>::type v = __builtin_nontemporal_load(src + c * L);
+        if constexpr (CPLX) {
+#pragma unroll
+            for (int e = 0; e < K; e += 2) {
+                const int s = c * K + e;
+                if (s < S) {
+                    const int el = s / 2, r = el / NO, col = el % NO;
+                    const T br = v[e], bi = v[e + 1];
+                    const T xr = xv[2 * col], xi = xv[2 * col + 1];
+                    acc[2 * r] = fma(br, xr, acc[2 * r]);
+                    acc[2 * r] = fma(-bi, xi, acc[2 * r]);
+                    acc[2 * r + 1] = fma(br, xi, acc[2 * r + 1]);
+                    acc[2 * r + 1] = fma(bi, xr, acc[2 * r + 1]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < K; ++e) {
+                const int s = c * K + e;
+                if (s < S) {
+                    const int r = s / NO, col = s % NO;
+                    acc[r] = fma(v[e], xv[col], acc[r]);
+                }
+            }
+        }
+    }
+}
+
+struct HxK {
+    const void* blocks;
+    const int32_t* nbr;
+    const void* x;
+    void* y;
+    const double* pot;
+    const void* xprev;
+    const double* beta;
+    double* partial;
+    int64_t n_atoms;
+    int64_t n_tiles;
+};
+
+template <typename T, bool CPLX, int NO, int R, bool DIAG, bool LZ>
+__global__ __launch_bounds__(256) void hx_kernel(HxK a) {
+    constexpr int CS = CPLX ? 2 : 1;
+    constexpr int G = NO / R, A = 64 / G, L = A * G;
+    constexpr int K = 16 / sizeof(T);
+    constexpr int BC = (R * NO * CS + K - 1) / K;
+    constexpr int ROW = NO * CS;                     // scalars per atom row block
+    constexpr int ROWB = ROW * sizeof(T);
+    constexpr int OWN = R * CS;                      // scalars this lane owns
+    typedef typename Vec16<T>::type V;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t tile = blk * 4 + wave;
+    const int64_t atom = tile * A + lane / G;
+    const int g = lane % G;
+    const bool active = tile < a.n_tiles && lane < L && atom < a.n_atoms;
+
+    const T* __restrict__ x = static_cast<const T*>(a.x);
+    T acc[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) acc[k] = T(0);
+    double pa = 0.0, pw = 0.0;
+
+    if (active) {
+        const V* src = static_cast<const V*>(a.blocks) + (tile * (4 * BC + (DIAG ? (R + K - 1) / K : BC))) * L + lane;
+        int32_t nb[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) nb[b] = a.nbr[atom * 4 + b];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (nb[b] >= 0) {
+                T xv[ROW];
+                load_row<T, ROW, ROWB>(x + int64_t(nb[b]) * ROW, xv);
+                stream_rows<T, CPLX, NO, R>(src + b * BC * L, L, xv, acc);
+            }
+        }
+        const V* osrc = src + 4 * BC * L;
+        T xo[OWN];
+        load_row<T, OWN, (R * CS * sizeof(T)) % 16 == 0 && ROWB % 16 == 0 ? 16 : ((R * CS * sizeof(T)) % 8 == 0 && ROWB % 8 == 0 ? 8 : 4)>(
+            x + atom * ROW + g * OWN, xo);
+        if constexpr (DIAG) {
+            constexpr int OC = (R + K - 1) / K;
+#pragma unroll
+            for (int c = 0; c < OC; ++c) {
+                const V v = __builtin_nontemporal_load(osrc + c * L);
+#pragma unroll
+                for (int e = 0; e < K; ++e) {
+                    const int r = c * K + e;
+                    if (r < R) {
+#pragma unroll
+                        for (int q = 0; q < CS; ++q) acc[r * CS + q] = fma(v[e], xo[r * CS + q], acc[r * CS + q]);
+                    }
+                }
+            }
+        } else {
+            T xa[ROW];
+            load_row<T, ROW, ROWB>(x + atom * ROW, xa);
+            stream_rows<T, CPLX, NO, R>(osrc, L, xa, acc);
+        }
+        if (a.pot) {
+            const T u = T(a.pot[atom]);
+#pragma unroll
+            for (int k = 0; k < OWN; ++k) acc[k] = fma(u, xo[k], acc[k]);
+        }
+        if constexpr (LZ) {
+            if (a.xprev) {
+                const T bt = T(*a.beta);
+                T xp[OWN];
+                load_row<T, OWN, 4>(static_cast<const T*>(a.xprev) + atom * ROW + g * OWN, xp);
+#pragma unroll
+                for (int k = 0; k < OWN; ++k) acc[k] = fma(-bt, xp[k], acc[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < OWN; ++k) {
+                pa += double(xo[k]) * double(acc[k]);
+                pw += double(acc[k]) * double(acc[k]);
+            }
+        }
+        store_row<T, OWN, (R * CS * sizeof(T)) % 16 == 0 && ROWB % 16 == 0 ? 16 : ((R * CS * sizeof(T)) % 8 == 0 && ROWB % 8 == 0 ? 8 : 4)>(
+            static_cast<T*>(a.y) + atom * ROW + g * OWN, acc);
+    }
+    if constexpr (LZ) {
+        // Re(x^H y) = sum over real scalars of x*y for interleaved complex
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            pa += __shfl_xor(pa, off, 64);
+            pw += __shfl_xor(pw, off, 64);
+        }
+        __shared__ double red[4][2];
+        if (lane == 0) {
+            red[wave][0] = pa;
+            red[wave][1] = pw;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && a.partial) {
+            a.partial[2 * blockIdx.x] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+            a.partial[2 * blockIdx.x + 1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+        }
+    }
+}
+
+template <typename T, bool CPLX, int NO, int R, bool DIAG>
+void launch_one(const Layout& lay, const HxArgs& h, hipStream_t s) {
+    HxK k;
+    k.blocks = h.blocks;
+    k.nbr = h.nbr;
+    k.x = h.x;
+    k.y = h.y;
+    k.pot = h.pot;
+    k.xprev = h.xprev;
+    k.beta = h.beta;
+    k.partial = h.partial;
+    k.n_atoms = h.n_atoms;
+    k.n_tiles = lay.n_tiles;
+    const int64_t nblk = (lay.n_tiles + 3) / 4;
+    if (nblk == 0) return;
+    if (h.partial)
+        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, true>), dim3(nblk), dim3(256), 0, s, k);
+    else
+        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, false>), dim3(nblk), dim3(256), 0, s, k);
+}
+
+template <typename T, bool CPLX, int NO, int R>
+void launch_diag(const Layout& lay, const HxArgs& h, hipStream_t s) {
+    if (lay.diag)
+        launch_one<T, CPLX, NO, R, true>(lay, h, s);
+    else
+        launch_one<T, CPLX, NO, R, false>(lay, h, s);
+}
+
+template <typename T, bool CPLX>
+void launch_shape(const Layout& lay, const HxArgs& h, hipStream_t s) {
+    const int no = lay.n_o, r = lay.R;
+#define TBH_CASE(NO_, R_)                                   \
+    if (no == NO_ && r == R_) {                             \
+        launch_diag<T, CPLX, NO_, R_>(lay, h, s);           \
+        return;                                             \
+    }
+    TBH_CASE(5, 5)
+    TBH_CASE(5, 1)
+    TBH_CASE(10, 10)
+    TBH_CASE(10, 5)
+    TBH_CASE(10, 2)
+    if constexpr (CPLX) {
+        TBH_CASE(20, 20)
+        TBH_CASE(20, 10)
+        TBH_CASE(20, 4)
+    }
+#undef TBH_CASE
+    throw Error(TBH_EINVAL, "no H.x kernel for n_o=" + std::to_string(no) + " rows/lane=" + std::to_string(r));
+}
+
+}  // namespace
+
+bool hx_shape_supported(int n_o, bool cplx_h, int R) {
+    if (n_o == 5) return R == 5 || R == 1;
+    if (n_o == 10) return R == 10 || R == 5 || R == 2;
+    if (n_o == 20) return cplx_h && (R == 20 || R == 10 || R == 4);
+    return false;
+}
+
+int64_t hx_num_blocks(const Layout& lay) { return (lay.n_tiles + 3) / 4; }
+
+void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
+    const bool c = lay.cs == 2;
+    if (f64) {
+        if (c) launch_shape<double, true>(lay, h, s);
+        else launch_shape<double, false>(lay, h, s);
+    } else {
+        if (c) launch_shape<float, true>(lay, h, s);
+        else launch_shape<float, false>(lay, h, s);
+    }
+    TBH_HIP(hipGetLastError());
+}
+
+}  // namespace tbh

@@ -1,0 +1,165 @@
+// Internal declarations shared by the host builder, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tbh.h"
+
+namespace tbh {
+
+using cplx = std::complex<double>;
+
+// An error that crosses back to the C ABI as a status code + message.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define TBH_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess)                                                      \
+            throw ::tbh::Error(TBH_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TBH_REQUIRE(cond, msg)                                                     \
+    do {                                                                           \
+        if (!(cond)) throw ::tbh::Error(TBH_EINVAL, msg);                         \
+    } while (0)
+
+// Device buffer owned by the library.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n) {
+        if (n <= bytes && p) return;
+        release();
+        if (n == 0) return;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            p = nullptr;
+            throw Error(TBH_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// host model builder
+// ---------------------------------------------------------------------------
+struct HostModel {
+    int64_t n = 0;
+    int n_base = 0, n_o = 0;
+    bool spin = false, cplx_h = false;
+    std::vector<int32_t> nbr;     // [n][4]
+    std::vector<int8_t> wrap;     // [n][4][3]
+    std::vector<uint8_t> sub;     // 0 = A, 1 = B
+    int64_t n_dangling = 0;
+    // inputs kept for block assembly
+    tbh_params par{};
+    std::vector<double> onsite_par, sk_par, so_par;
+    std::vector<uint8_t> species;
+    std::vector<double> bond_scale;   // [n][4] or empty
+    std::vector<double> pot;          // [n] or empty
+    double kfrac[3] = {0, 0, 0};
+};
+
+// Validate inputs, find neighbours.  Throws Error on invalid geometry.
+void host_prepare(const tbh_geometry* g, const tbh_params* p, const tbh_build_opts* o,
+                  HostModel& m);
+// Assemble the FP64 blocks of atom i: onsite [n_o*n_o], bonds [4][n_o*n_o].
+void host_atom_blocks(const HostModel& m, int64_t i, cplx* onsite, cplx* bonds);
+// Slater-Koster two-centre block (n_base x n_base, row-major) for the unit
+// direction (l, m, n) with the 14 canonical integrals V.
+void sk_block_closed_form(int model, const double* V, double l, double m, double n, double* out);
+
+// ---------------------------------------------------------------------------
+// packed layout streamed by the H.x kernels
+//
+// Each lane of a 64-wide wavefront owns R consecutive rows of one atom;
+// G = n_o / R lanes share an atom and a tile holds A = 64 / G atoms
+// (L = A * G active lanes).  A lane's private stream is: for each bond slot
+// b, its R rows of B_ib (R * n_o elements, padded to whole 16-byte chunks),
+// then its R rows of the on-site block (dense) or its R diagonal entries
+// (diagonal).  Streams are interleaved chunk-major across the tile's lanes
+// so that every chunk of a wavefront is one contiguous L*16-byte read:
+//   byte offset of (tile t, chunk c, lane l) = ((t * C + c) * L + l) * 16.
+// ---------------------------------------------------------------------------
+struct Layout {
+    int n_o = 0, R = 0, G = 0, A = 0, L = 0;
+    int cs = 1;            // scalars per element (2 for complex)
+    int esz = 4;           // bytes per scalar
+    int K = 4;             // scalars per 16-byte chunk
+    int bond_chunks = 0;   // chunks per bond segment
+    int onsite_chunks = 0; // chunks of the on-site segment
+    int C = 0;             // chunks per lane
+    bool diag = false;
+    int64_t n_tiles = 0;
+    int64_t bytes = 0;
+};
+Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
+// Pack atoms into the layout (T = float or double).
+void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst);
+
+// ---------------------------------------------------------------------------
+// the Hamiltonian object
+// ---------------------------------------------------------------------------
+struct Ctx;
+struct Ham {
+    Ctx* ctx = nullptr;
+    int64_t n = 0, dim = 0;
+    int n_o = 0, n_base = 0;
+    bool cplx_h = false, spin = false;
+    int prec = TBH_F32;
+    bool diag = false;
+    int64_t n_dangling = 0;
+    Layout lay, lay64;
+    DevBuf blocks, blocks64, nbr_d, pot_d;
+    bool has_f64 = false, has_pot = false;
+    std::vector<int32_t> nbr_h;
+    std::vector<int8_t> wrap_h;
+    int64_t hx_bytes() const;
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevBuf partial, scal;  // reduction scratch
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (hx.hip)
+// ---------------------------------------------------------------------------
+struct HxArgs {
+    const void* blocks = nullptr;
+    const int32_t* nbr = nullptr;
+    const void* x = nullptr;
+    void* y = nullptr;
+    const double* pot = nullptr;     // per-atom potential (FP64) or null
+    int64_t n_atoms = 0;
+    // Lanczos epilogue: y = H x - beta * xprev; partials of Re(x^H y), |y|^2
+    const void* xprev = nullptr;
+    const double* beta = nullptr;    // device scalar (null: 0)
+    double* partial = nullptr;       // [n_blocks][2] or null
+};
+// Number of workgroups a launch of the layout uses (for partial buffers).
+int64_t hx_num_blocks(const Layout& lay);
+bool hx_shape_supported(int n_o, bool cplx_h, int R);
+void hx_launch(const Layout& lay, bool f64, const HxArgs& a, hipStream_t s);
+
+}  // namespace tbh

@@ -193,3 +193,14 @@ def test_time_reversal_real_model():
     a = np.linalg.eigvalsh(T.hamiltonian(_cube(2, kfrac=kf)).toarray())
     b = np.linalg.eigvalsh(T.hamiltonian(_cube(2, kfrac=-kf)).toarray())
     assert np.abs(a - b).max() < 1e-11
+
+
+def test_hx_rows_match_csr():
+    p = _cube(2, model=W.MODEL_SP3D5S, spin=1, strain=True, potential=0.2,
+              kfrac=(0.1, 0.0, -0.2))
+    H = T.hamiltonian(p)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(p.dim) + 1j * rng.standard_normal(p.dim)
+    y = (H @ x).reshape(p.n_atoms, -1)
+    atoms = [0, 5, 17, 63]
+    assert np.abs(T.hx_rows(p, atoms, x) - y[atoms]).max() < 1e-12
