@@ -187,6 +187,67 @@ int tbh_apply_h(tbh_ham* h, const void* x, void* y, int32_t nrhs);
 /* y = H x in FP64 with the FP64 copy (or the main copy for TBH_F64). */
 int tbh_apply_h_f64(tbh_ham* h, const double* x, double* y);
 
+
+/* ------------------------------------------------------------------------
+ * Lanczos eigensolver (Sec. III-A, item 1; the iteration count of Sec.
+ * II-B is its unit of cost).
+ *
+ * Recurrence (j = 0..m-1, v_0 = v0/|v0|, beta_0 = 0):
+ *   w = H v_j - beta_j v_{j-1};  alpha_j = Re(v_j^H w);  w -= alpha_j v_j;
+ *   [reorth: twice { c = V^H w; w -= V c } over v_0..v_j, FP64 coefficients]
+ *   beta_{j+1} = |w|;  breakdown if beta_{j+1} <= 1e-12 max|T|;
+ *   v_{j+1} = w / beta_{j+1}.
+ * Vectors are stored in the ham's precision; every inner product,
+ * reorthogonalisation coefficient and the tridiagonal eigensolve are FP64.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double sigma;          /* target energy (eV) */
+    int32_t k;             /* distinct eigenvalues wanted (>= 1) */
+    int32_t max_iter;      /* Lanczos steps m (1..100000) */
+    int32_t reorth;        /* 0: none (three vectors); 1: full CGS2 (m+1 vectors) */
+    int32_t n_cand;        /* Ritz pairs examined; 0 = min(m, max(4k, k+16)) */
+    double res_tol;        /* converged iff |H y - theta y| <= res_tol, |y| = 1 (0 = 1e-4 eV) */
+    double merge_tol;      /* converged values closer than this are one eigenvalue (0 = 1e-6 eV) */
+    const double* v0;      /* host [dim] FP64 start vector (complex interleaved), not all zero */
+} tbh_lanczos_opts;
+
+typedef struct {
+    int32_t steps;         /* steps taken (fewer than max_iter after a breakdown) */
+    int32_t breakdown;     /* 1 if the recurrence stopped on an invariant subspace */
+    int32_t n_found;       /* distinct converged eigenvalues reported (<= k) */
+    int32_t n_cand;        /* Ritz pairs examined */
+    double max_res;        /* largest residual among the reported values (eV) */
+    double seconds;        /* wall time of the call */
+    double hx_seconds;     /* device time of the H.x kernels of the recurrence (0 unless timed) */
+} tbh_lanczos_report;
+
+/* Eigenvalues nearest sigma.  Candidates are the n_cand Ritz values of T_m
+ * nearest sigma; each gets its Ritz vector y = V s, an explicit FP64
+ * residual |H y - theta y| and a Rayleigh-quotient refinement y^H H y with
+ * the FP64 copy of H (the ham must have one: TBH_F64, or TBH_F32 built with
+ * keep_f64).  Converged candidates within merge_tol are one eigenvalue; the
+ * k distinct converged values nearest sigma (ties: lower value) are returned
+ * in ascending order.
+ * Outputs (host, [k], may be NULL): evals = raw Ritz values, refined =
+ * Rayleigh quotients, res = residuals (eV), copies = converged copies merged
+ * into the value.  evecs_dev (device, may be NULL): [k][dim] FP64 unit Ritz
+ * vectors (complex interleaved).  Slots past n_found are set to NaN / 0.
+ * Returns TBH_ENOCONV (results written) if fewer than k values converged. */
+int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, double* refined,
+                     double* res, int32_t* copies, double* evecs_dev, tbh_lanczos_report* rep);
+
+/* The recurrence only: m steps from the host start vector v0 ([dim] FP64).
+ * alpha[m], beta[m] (host, may be NULL) receive alpha_j and beta_{j+1};
+ * entries past the last step are 0.  With time_hx != 0 the H.x kernels are
+ * bracketed by HIP events and their summed duration is reported. */
+int tbh_lanczos_run(tbh_ham* h, int32_t m, int32_t reorth, const double* v0, double* alpha,
+                    double* beta, int32_t time_hx, tbh_lanczos_report* rep);
+
+/* Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal
+ * diag[m] and off-diagonal off[m-1] (host arrays), by FP64 Sturm bisection
+ * on the context's device; theta[m] is host output. */
+int tbh_tridiag_eig(tbh_ctx* ctx, int32_t m, const double* diag, const double* off, double* theta);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,6 +55,18 @@ class tbh_ham_info(C.Structure):
                 ("n_dangling", C.c_int64), ("stored_bytes", C.c_int64), ("hx_bytes", C.c_int64)]
 
 
+class tbh_lanczos_opts(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("k", C.c_int32), ("max_iter", C.c_int32),
+                ("reorth", C.c_int32), ("n_cand", C.c_int32), ("res_tol", C.c_double),
+                ("merge_tol", C.c_double), ("v0", C.POINTER(C.c_double))]
+
+
+class tbh_lanczos_report(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("breakdown", C.c_int32), ("n_found", C.c_int32),
+                ("n_cand", C.c_int32), ("max_res", C.c_double), ("seconds", C.c_double),
+                ("hx_seconds", C.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -75,6 +87,11 @@ _SIGS = [
     ("tbh_ham_set_potential", C.c_int, [C.c_void_p, C.c_void_p]),
     ("tbh_apply_h", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("tbh_apply_h_f64", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("tbh_lanczos_eigs", C.c_int, [C.c_void_p, C.POINTER(tbh_lanczos_opts), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(tbh_lanczos_report)]),
+    ("tbh_lanczos_run", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int32, C.POINTER(tbh_lanczos_report)]),
+    ("tbh_tridiag_eig", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
 
 
@@ -306,3 +323,73 @@ def apply_h_f64(ham: Hamiltonian, x, y=None):
     _check_vec(ham, y, f64=True)
     _check(lib().tbh_apply_h_f64(ham.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
     return y
+
+
+def _report(r):
+    return {k: getattr(r, k) for k, _ in tbh_lanczos_report._fields_}
+
+
+def _v0_host(ham, v0):
+    v = np.asarray(v0)
+    if np.iscomplexobj(v):
+        v = np.ascontiguousarray(v, dtype=np.complex128).view(np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64).ravel()
+    if v.size != ham.dim * (2 if ham.is_complex else 1):
+        raise ValueError("start vector length must equal dim (complex: 2*dim reals)")
+    return v
+
+
+def lanczos_run(ham: Hamiltonian, m: int, v0, reorth: bool = False, time_hx: bool = False):
+    """The Lanczos recurrence alone (m steps).  Returns (alpha, beta, report)
+    with beta[j] = beta_{j+1}."""
+    v = _v0_host(ham, v0)
+    a = np.zeros(m)
+    b = np.zeros(m)
+    rep = tbh_lanczos_report()
+    _check(lib().tbh_lanczos_run(ham.h, int(m), int(bool(reorth)), v.ctypes.data, a.ctypes.data,
+                                 b.ctypes.data, int(bool(time_hx)), C.byref(rep)))
+    r = _report(rep)
+    return a[:r["steps"]], b[:r["steps"]], r
+
+
+def lanczos_eigs(ham: Hamiltonian, sigma: float, k: int, max_iter: int, v0, reorth: bool = True,
+                 n_cand: int = 0, res_tol: float = 0.0, merge_tol: float = 0.0,
+                 want_vectors: bool = False, allow_partial: bool = True):
+    """Distinct converged eigenvalues nearest sigma.  Returns a dict with
+    evals (raw Ritz values), refined (FP64 Rayleigh quotients), res, copies,
+    report, and vectors ([k, dim] FP64/complex128 device tensor) if asked."""
+    import torch
+    v = _v0_host(ham, v0)
+    o = tbh_lanczos_opts(float(sigma), int(k), int(max_iter), int(bool(reorth)), int(n_cand),
+                         float(res_tol), float(merge_tol), v.ctypes.data_as(C.POINTER(C.c_double)))
+    ev = np.zeros(k)
+    rf = np.zeros(k)
+    rs = np.zeros(k)
+    cp = np.zeros(k, np.int32)
+    vec = None
+    if want_vectors:
+        vec = torch.zeros((k, ham.dim), dtype=torch.complex128 if ham.is_complex else torch.float64,
+                          device=f"cuda:{ham.ctx.device}")
+    rep = tbh_lanczos_report()
+    rc = lib().tbh_lanczos_eigs(ham.h, C.byref(o), ev.ctypes.data, rf.ctypes.data, rs.ctypes.data,
+                                cp.ctypes.data, None if vec is None else C.c_void_p(vec.data_ptr()),
+                                C.byref(rep))
+    if rc != TBH_OK and not (allow_partial and rc == TBH_ENOCONV):
+        _check(rc)
+    r = _report(rep)
+    n = r["n_found"]
+    out = dict(evals=ev[:n], refined=rf[:n], res=rs[:n], copies=cp[:n], report=r, status=rc)
+    if vec is not None:
+        out["vectors"] = vec[:n]
+    return out
+
+
+def tridiag_eig(ctx: Context, diag, off):
+    """Eigenvalues (ascending) of a symmetric tridiagonal matrix, FP64
+    bisection on the device."""
+    d = np.ascontiguousarray(diag, dtype=np.float64)
+    e = np.ascontiguousarray(off, dtype=np.float64)
+    th = np.zeros(d.size)
+    _check(lib().tbh_tridiag_eig(ctx.h, d.size, d.ctypes.data, e.ctypes.data if e.size else None,
+                                 th.ctypes.data))
+    return th

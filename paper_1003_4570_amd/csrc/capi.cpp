@@ -6,28 +6,13 @@
 
 namespace {
 thread_local std::string g_err;
-
-template <typename F>
-int guard(F&& f) {
-    try {
-        f();
-        g_err.clear();
-        return TBH_OK;
-    } catch (const tbh::Error& e) {
-        g_err = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_err = "host allocation failed";
-        return TBH_ENOMEM;
-    } catch (const std::exception& e) {
-        g_err = e.what();
-        return TBH_EINVAL;
-    }
-}
 }  // namespace
 
-struct tbh_ctx : tbh::Ctx {};
-struct tbh_ham : tbh::Ham {};
+namespace tbh {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace tbh
+
+using tbh::guard;
 
 namespace tbh {
 

@@ -162,4 +162,29 @@ int64_t hx_num_blocks(const Layout& lay);
 bool hx_shape_supported(int n_o, bool cplx_h, int R);
 void hx_launch(const Layout& lay, bool f64, const HxArgs& a, hipStream_t s);
 
+// error slot shared by every C ABI translation unit (thread-local)
+void set_error(const std::string& msg);
+
+// Run f, translating exceptions into a status code and the error message.
+template <typename F>
+int guard(F&& f) {
+    try {
+        f();
+        set_error("");
+        return TBH_OK;
+    } catch (const Error& e) {
+        set_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return TBH_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return TBH_EINVAL;
+    }
+}
+
 }  // namespace tbh
+
+struct tbh_ctx : tbh::Ctx {};
+struct tbh_ham : tbh::Ham {};
