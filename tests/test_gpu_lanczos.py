@@ -49,20 +49,27 @@ def test_tridiag_glued_wilkinson(ctx):
     assert np.abs(got - want).max() <= 1e-12 * 11
 
 
-def test_recurrence_fp64_matches_oracle(ctx):
-    p = W.c1_lanczos_fp64(0)
-    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p))
+@pytest.mark.parametrize("case", ["c1", "broken"])
+def test_recurrence_fp64_matches_oracle(ctx, case):
+    """alpha_j, beta_{j+1} against the oracle on the same v0.  Once a Ritz
+    value converges, later coefficients amplify rounding differences
+    exponentially (for both codes), so only the leading steps -- before the
+    first Ritz value converges on these cells -- are compared elementwise."""
+    if case == "c1":
+        p = W.c1_lanczos_fp64(0)
+    else:
+        p = W.problem_periodic_cube(2, seed=4, model=W.MODEL_SP3D5S, strain=True, potential=0.4)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64"))
     H = T.hamiltonian(p)
     a_o, b_o, _ = L.lanczos(lambda x: H @ x, p.v0, 60)
     a, b, rep = tbh.lanczos_run(h, 60, p.v0, reorth=True)
     assert rep["steps"] == 60
-    assert np.abs(a - a_o).max() < 1e-9
-    assert np.abs(b - b_o).max() < 1e-9
+    assert np.abs(a[:40] - a_o[:40]).max() < 1e-10
+    assert np.abs(b[:40] - b_o[:40]).max() < 1e-10
     a2, b2, _ = tbh.lanczos_run(h, 60, p.v0, reorth=False)
     a_o2, b_o2, _ = L.lanczos(lambda x: H @ x, p.v0, 60, reorth=False)
-    # without reorthogonalisation the coefficients agree until rounding grows
-    assert np.abs(a2[:20] - a_o2[:20]).max() < 1e-9
-    assert np.abs(b2[:20] - b_o2[:20]).max() < 1e-9
+    assert np.abs(a2[:20] - a_o2[:20]).max() < 1e-10
+    assert np.abs(b2[:20] - b_o2[:20]).max() < 1e-10
 
 
 def _distinct(ev, tol=1e-8):
