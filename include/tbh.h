@@ -208,7 +208,9 @@ typedef struct {
     int32_t n_cand;        /* Ritz pairs examined; 0 = min(m, max(4k, k+16)) */
     double res_tol;        /* converged iff |H y - theta y| <= res_tol, |y| = 1 (0 = 1e-4 eV) */
     double merge_tol;      /* converged values closer than this are one eigenvalue (0 = 1e-6 eV) */
-    const double* v0;      /* host [dim] FP64 start vector (complex interleaved), not all zero */
+    const double* v0;      /* host [dim] FP64 start vector (complex interleaved), not all
+                              zero; or NULL to use v0_dev */
+    const double* v0_dev;  /* device [dim] FP64 start vector, used when v0 is NULL */
 } tbh_lanczos_opts;
 
 typedef struct {
@@ -236,12 +238,14 @@ typedef struct {
 int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, double* refined,
                      double* res, int32_t* copies, double* evecs_dev, tbh_lanczos_report* rep);
 
-/* The recurrence only: m steps from the host start vector v0 ([dim] FP64).
- * alpha[m], beta[m] (host, may be NULL) receive alpha_j and beta_{j+1};
- * entries past the last step are 0.  With time_hx != 0 the H.x kernels are
- * bracketed by HIP events and their summed duration is reported. */
-int tbh_lanczos_run(tbh_ham* h, int32_t m, int32_t reorth, const double* v0, double* alpha,
-                    double* beta, int32_t time_hx, tbh_lanczos_report* rep);
+/* The recurrence only: o->max_iter steps (o->reorth) from o->v0 / o->v0_dev;
+ * sigma, k and the tolerances are ignored.  alpha[m], beta[m] (host, may be
+ * NULL) receive alpha_j and beta_{j+1}; entries past the last step are 0.
+ * With time_hx != 0 the H.x kernels are bracketed by HIP events and their
+ * summed duration is reported.  The ham keeps the Lanczos workspace between
+ * calls with the same m and reorth, so repeated runs allocate nothing. */
+int tbh_lanczos_run(tbh_ham* h, const tbh_lanczos_opts* o, double* alpha, double* beta,
+                    int32_t time_hx, tbh_lanczos_report* rep);
 
 /* Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal
  * diag[m] and off-diagonal off[m-1] (host arrays), by FP64 Sturm bisection

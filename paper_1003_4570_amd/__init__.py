@@ -58,7 +58,8 @@ class tbh_ham_info(C.Structure):
 class tbh_lanczos_opts(C.Structure):
     _fields_ = [("sigma", C.c_double), ("k", C.c_int32), ("max_iter", C.c_int32),
                 ("reorth", C.c_int32), ("n_cand", C.c_int32), ("res_tol", C.c_double),
-                ("merge_tol", C.c_double), ("v0", C.POINTER(C.c_double))]
+                ("merge_tol", C.c_double), ("v0", C.POINTER(C.c_double)),
+                ("v0_dev", C.c_void_p)]
 
 
 class tbh_lanczos_report(C.Structure):
@@ -89,7 +90,7 @@ _SIGS = [
     ("tbh_apply_h_f64", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("tbh_lanczos_eigs", C.c_int, [C.c_void_p, C.POINTER(tbh_lanczos_opts), C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(tbh_lanczos_report)]),
-    ("tbh_lanczos_run", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+    ("tbh_lanczos_run", C.c_int, [C.c_void_p, C.POINTER(tbh_lanczos_opts), C.c_void_p,
                                   C.c_void_p, C.c_int32, C.POINTER(tbh_lanczos_report)]),
     ("tbh_tridiag_eig", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
@@ -329,6 +330,22 @@ def _report(r):
     return {k: getattr(r, k) for k, _ in tbh_lanczos_report._fields_}
 
 
+def _v0_args(ham, v0):
+    """(host array or None, device pointer or None) for a start vector given
+    as a numpy array (host) or an FP64 / complex128 device tensor."""
+    try:
+        import torch
+        if isinstance(v0, torch.Tensor):
+            if not v0.is_cuda or v0.dtype not in (torch.float64, torch.complex128) or not v0.is_contiguous():
+                raise TypeError("device start vector must be a contiguous float64/complex128 tensor")
+            if v0.numel() * (2 if v0.is_complex() else 1) != ham.dim * (2 if ham.is_complex else 1):
+                raise ValueError("start vector length must equal dim")
+            return None, C.c_void_p(v0.data_ptr())
+    except ImportError:
+        pass
+    return _v0_host(ham, v0), None
+
+
 def _v0_host(ham, v0):
     v = np.asarray(v0)
     if np.iscomplexobj(v):
@@ -342,12 +359,14 @@ def _v0_host(ham, v0):
 def lanczos_run(ham: Hamiltonian, m: int, v0, reorth: bool = False, time_hx: bool = False):
     """The Lanczos recurrence alone (m steps).  Returns (alpha, beta, report)
     with beta[j] = beta_{j+1}."""
-    v = _v0_host(ham, v0)
+    v, vd = _v0_args(ham, v0)
+    o = tbh_lanczos_opts(0.0, 1, int(m), int(bool(reorth)), 0, 0.0, 0.0,
+                         None if v is None else v.ctypes.data_as(C.POINTER(C.c_double)), vd)
     a = np.zeros(m)
     b = np.zeros(m)
     rep = tbh_lanczos_report()
-    _check(lib().tbh_lanczos_run(ham.h, int(m), int(bool(reorth)), v.ctypes.data, a.ctypes.data,
-                                 b.ctypes.data, int(bool(time_hx)), C.byref(rep)))
+    _check(lib().tbh_lanczos_run(ham.h, C.byref(o), a.ctypes.data, b.ctypes.data,
+                                 int(bool(time_hx)), C.byref(rep)))
     r = _report(rep)
     return a[:r["steps"]], b[:r["steps"]], r
 
@@ -359,9 +378,10 @@ def lanczos_eigs(ham: Hamiltonian, sigma: float, k: int, max_iter: int, v0, reor
     evals (raw Ritz values), refined (FP64 Rayleigh quotients), res, copies,
     report, and vectors ([k, dim] FP64/complex128 device tensor) if asked."""
     import torch
-    v = _v0_host(ham, v0)
+    v, vd = _v0_args(ham, v0)
     o = tbh_lanczos_opts(float(sigma), int(k), int(max_iter), int(bool(reorth)), int(n_cand),
-                         float(res_tol), float(merge_tol), v.ctypes.data_as(C.POINTER(C.c_double)))
+                         float(res_tol), float(merge_tol),
+                         None if v is None else v.ctypes.data_as(C.POINTER(C.c_double)), vd)
     ev = np.zeros(k)
     rf = np.zeros(k)
     rs = np.zeros(k)

@@ -47,34 +47,46 @@ std::vector<std::pair<int, int>> select_converged(const std::vector<Cand>& cs, d
     return reps;
 }
 
-void upload_v0(tbh::Ham& h, const double* v0, tbh::DevBuf& buf) {
-    TBH_REQUIRE(v0, "null start vector");
+// device pointer of the FP64 start vector (uploaded into buf when given on the host)
+const double* start_vector(tbh::Ham& h, const tbh_lanczos_opts* o, tbh::DevBuf& buf) {
+    if (!o->v0) {
+        TBH_REQUIRE(o->v0_dev, "null start vector (v0 and v0_dev)");
+        return o->v0_dev;
+    }
+    const double* v0 = o->v0;
     const size_t ns = size_t(h.dim) * (h.cplx_h ? 2 : 1);
     double nrm = 0.0;
     for (size_t i = 0; i < ns; ++i) nrm += v0[i] * v0[i];
     TBH_REQUIRE(nrm > 0.0 && std::isfinite(nrm), "start vector is zero or not finite");
     buf.alloc(ns * sizeof(double));
     TBH_HIP(hipMemcpyAsync(buf.p, v0, ns * sizeof(double), hipMemcpyHostToDevice, h.ctx->stream));
+    return buf.as<double>();
+}
+
+tbh::LzWork& workspace(tbh::Ham& h) {
+    if (!h.lz) h.lz = std::make_shared<tbh::LzWork>();
+    return *h.lz;
 }
 
 }  // namespace
 
 extern "C" {
 
-int tbh_lanczos_run(tbh_ham* h, int32_t m, int32_t reorth, const double* v0, double* alpha, double* beta,
-                    int32_t time_hx, tbh_lanczos_report* rep) {
+int tbh_lanczos_run(tbh_ham* h, const tbh_lanczos_opts* o, double* alpha, double* beta, int32_t time_hx,
+                    tbh_lanczos_report* rep) {
     return guard([&] {
-        TBH_REQUIRE(h, "null ham");
+        TBH_REQUIRE(h && o, "null argument");
+        const int m = o->max_iter, reorth = o->reorth;
         TBH_REQUIRE(m >= 1 && m <= 100000, "max_iter must be in 1..100000");
         TBH_REQUIRE(reorth == 0 || reorth == 1, "reorth must be 0 or 1");
         TBH_HIP(hipSetDevice(h->ctx->device));
         const auto t0 = std::chrono::steady_clock::now();
         tbh::DevBuf v0d;
-        upload_v0(*h, v0, v0d);
-        tbh::LzWork W;
+        const double* v0 = start_vector(*h, o, v0d);
+        tbh::LzWork& W = workspace(*h);
         int steps = 0, brk = 0;
         double hx_ms = 0.0;
-        tbh::lanczos_recurrence(*h, W, m, reorth != 0, v0d.as<double>(), alpha, beta, &steps, &brk,
+        tbh::lanczos_recurrence(*h, W, m, reorth != 0, v0, alpha, beta, &steps, &brk,
                                 time_hx ? &hx_ms : nullptr);
         if (rep) {
             *rep = tbh_lanczos_report{};
@@ -100,11 +112,11 @@ int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, doubl
         const double res_tol = o->res_tol > 0 ? o->res_tol : 1e-4;
         const double merge_tol = o->merge_tol > 0 ? o->merge_tol : 1e-6;
         tbh::DevBuf v0d;
-        upload_v0(*h, o->v0, v0d);
-        tbh::LzWork W;
+        const double* v0 = start_vector(*h, o, v0d);
+        tbh::LzWork& W = workspace(*h);
         int steps = 0, brk = 0;
-        tbh::lanczos_recurrence(*h, W, o->max_iter, o->reorth != 0, v0d.as<double>(), nullptr, nullptr, &steps,
-                                &brk, nullptr);
+        tbh::lanczos_recurrence(*h, W, o->max_iter, o->reorth != 0, v0, nullptr, nullptr, &steps, &brk,
+                                nullptr);
         TBH_REQUIRE(steps >= 1, "Lanczos made no step");
         int ncand = o->n_cand > 0 ? o->n_cand : std::min(steps, std::max(4 * o->k, o->k + 16));
         ncand = std::min(ncand, steps);

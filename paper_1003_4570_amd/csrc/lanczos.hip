@@ -492,6 +492,7 @@ int64_t grid_for(int64_t n) {
 LzWork::~LzWork() = default;
 
 void LzWork::ensure(const Ham& h, int m, bool reorth) {
+    if (this->m == m && this->reorth == reorth && V.p) return;
     const int64_t ns = h.dim * (h.cplx_h ? 2 : 1);
     const size_t esz = h.prec == TBH_F64 ? 8 : 4;
     TBH_REQUIRE(!reorth || m <= 4000, "full reorthogonalisation supports at most 4000 steps");

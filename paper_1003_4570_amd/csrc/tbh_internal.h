@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <memory>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -120,6 +121,7 @@ void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst);
 // the Hamiltonian object
 // ---------------------------------------------------------------------------
 struct Ctx;
+struct LzWork;
 struct Ham {
     Ctx* ctx = nullptr;
     int64_t n = 0, dim = 0;
@@ -133,6 +135,7 @@ struct Ham {
     bool has_f64 = false, has_pot = false;
     std::vector<int32_t> nbr_h;
     std::vector<int8_t> wrap_h;
+    std::shared_ptr<LzWork> lz;   // Lanczos workspace kept between calls
     int64_t hx_bytes() const;
 };
 
