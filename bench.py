@@ -10,9 +10,10 @@ atoms), sp3d5s* without spin (10 orbitals, real symmetric H of dimension
 reorthogonalisation.  Inputs (H, start vector) are resident in HBM before the
 timed region.
 
-value = algorithmic H.x bytes moved per second over the whole timed job
-(packed H + neighbour table + x once + y once, per H.x, times the number of
-H.x), the Lanczos vector updates and reductions included in the time.
+value = algorithmic bytes of the fused Lanczos H.x moved per second over the
+whole timed job (packed H + neighbour table + x once + y once + x_prev once,
+per iteration, times the iterations), the Lanczos vector updates and
+reductions included in the time.
 
 roofline: the fused Lanczos H.x kernel's algorithmic bytes per launch over
 its average launch duration, timed with HIP events on the stream it runs on;
@@ -134,7 +135,8 @@ def main():
     ctx = tbh.Context(0)
     ham = tbh.build_hamiltonian(ctx, **tbh.problem_args(prob))
     v0 = torch.tensor(prob.v0, dtype=torch.float64, device="cuda")
-    hx_bytes = ham.info["hx_bytes"]
+    # the fused step kernel also reads x_prev (the beta_j v_{j-1} term)
+    hx_bytes = ham.info["hx_bytes"] + ham.info["dim"] * 4
     torch.cuda.synchronize()
 
     for _ in range(a.warmup):
