@@ -252,6 +252,90 @@ int tbh_lanczos_run(tbh_ham* h, const tbh_lanczos_opts* o, double* alpha, double
  * on the context's device; theta[m] is host output. */
 int tbh_tridiag_eig(tbh_ctx* ctx, int32_t m, const double* diag, const double* off, double* theta);
 
+/* ------------------------------------------------------------------------
+ * Finite-difference Poisson solver (Sec. III-A, item 3).
+ *
+ * Grid nodes [nz][ny][nx] with spacing h_nm, periodic in x and y, phi = 0 on
+ * the ghost planes z = -1 and z = nz; 7-point Laplacian:
+ *   -eps0 eps_r Lap_h phi = rho    (phi in V, rho in e/nm^3)
+ * ------------------------------------------------------------------------ */
+
+/* FP64 conjugate gradients for phi.  rho_dev, phi_dev: device
+ * [nz][ny][nx] FP64; phi_dev holds the initial guess on entry and the
+ * solution on return.  Stops when |r| <= rel_tol |b| or after max_iter
+ * iterations (then TBH_ENOCONV with the partial solution written). */
+int tbh_poisson_solve(tbh_ctx* ctx, const int32_t grid[3], double h_nm, double eps_r, const double* rho_dev,
+                      double* phi_dev, double rel_tol, int32_t max_iter, int32_t* iters,
+                      double* rel_res);
+
+/* ------------------------------------------------------------------------
+ * Self-consistent Schrodinger-Poisson loop (Sec. III-A; the application of
+ * Sec. III-B is a P delta layer in Si at 4 K).
+ *
+ * One step with input potential energy U (eV, on the grid; atom (qx,qy,qz)
+ * sits on node (qx,qy,qz)):
+ *  1. H(U) = H_TB + U at every atom's orbitals;
+ *  2. Lanczos (full CGS2, lanczos_iter steps) targeted at e_cbm + min U; the
+ *     n_cand Ritz pairs nearest the target with residual <= res_tol are the
+ *     states, their energies the FP64 Rayleigh quotients;
+ *  3. conduction-band-like states (E - <psi|U|psi> > sigma_mid) are filled
+ *     with spin degeneracy 2 and Fermi-Dirac occupation at T_K; the Fermi
+ *     level comes from neutrality (2 sum f = n_donors) unless fermi_fixed is
+ *     given (not NaN);
+ *  4. rho = e (donors - electrons) / h^3 at the nodes, U_out = -phi from the
+ *     Poisson solve (CG from the previous solution);
+ *  5. residual = max |U_out - U|; U <- U + mix_alpha (U_out - U).
+ * ------------------------------------------------------------------------ */
+typedef struct tbh_scf tbh_scf;
+
+typedef struct {
+    int32_t grid[3];          /* nx, ny, nz nodes (must contain every atom position) */
+    double h_nm;              /* grid spacing in nm (a/4 for the Si lattice) */
+    double eps_r;             /* relative permittivity */
+    double T_K;               /* temperature; 0 = step occupation */
+    double mix_alpha;         /* linear mixing factor, (0, 1] */
+    double tol_eV;            /* converged when max |U_out - U| < tol_eV */
+    double sigma_mid;         /* gap centre of the bulk bands (CB-like test) */
+    double e_cbm;             /* bulk conduction-band minimum (Lanczos target offset) */
+    double fermi_fixed;       /* NaN: Fermi level from neutrality; else this Fermi level */
+    int32_t n_cand;           /* Ritz pairs per eigen-solve */
+    int32_t lanczos_iter;     /* Lanczos steps per eigen-solve (>= n_cand, <= 4000) */
+    double res_tol;           /* residual (eV) for a Ritz pair to count as a state */
+    double cg_tol;            /* Poisson CG relative residual */
+    int32_t cg_max_iter;
+    const int32_t* donor_atoms;  /* host [n_donors]: atoms carrying a +e donor ion */
+    int32_t n_donors;         /* also the electron count (neutrality) */
+    const double* v0;         /* host [dim] FP64 Lanczos start vector (complex interleaved) */
+} tbh_scf_opts;
+
+typedef struct {
+    int32_t iterations;       /* steps taken so far */
+    int32_t converged;        /* residual < tol_eV at the last step */
+    double residual;          /* max |U_out - U| of the last step (eV) */
+    double fermi;             /* Fermi level (eV) */
+    int32_t n_cb;             /* states filled (CB-like, converged) */
+    int32_t n_conv;           /* converged Ritz pairs */
+    double electrons;         /* 2 sum f over the filled states */
+    int32_t cg_iters;
+    double cg_rel_res;
+    int32_t lanczos_steps;
+    double u_min;             /* min U after the update (eV) */
+    double seconds, eig_seconds, poisson_seconds;
+} tbh_scf_report;
+
+/* The SCF object keeps h (which must outlive it, and must have an FP64 copy)
+ * and owns its grid buffers.  The start potential is zero. */
+int tbh_scf_create(tbh_ham* h, const tbh_scf_opts* o, tbh_scf** out);
+int tbh_scf_destroy(tbh_scf* s);
+/* Set U (device [nz][ny][nx] FP64, eV), or NULL = 0 (the plain start). */
+int tbh_scf_set_potential(tbh_scf* s, const double* U_dev);
+/* Copy the current U into U_dev (device [nz][ny][nx] FP64). */
+int tbh_scf_get_potential(tbh_scf* s, double* U_dev);
+/* One self-consistency step; rep (host) receives the step's report. */
+int tbh_scf_step(tbh_scf* s, tbh_scf_report* rep);
+/* Steps until converged or max_iter steps; TBH_ENOCONV if not converged. */
+int tbh_scf_run(tbh_scf* s, int32_t max_iter, tbh_scf_report* rep);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,24 @@ class tbh_lanczos_report(C.Structure):
                 ("hx_seconds", C.c_double)]
 
 
+class tbh_scf_opts(C.Structure):
+    _fields_ = [("grid", C.c_int32 * 3), ("h_nm", C.c_double), ("eps_r", C.c_double),
+                ("T_K", C.c_double), ("mix_alpha", C.c_double), ("tol_eV", C.c_double),
+                ("sigma_mid", C.c_double), ("e_cbm", C.c_double), ("fermi_fixed", C.c_double),
+                ("n_cand", C.c_int32), ("lanczos_iter", C.c_int32), ("res_tol", C.c_double),
+                ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("donor_atoms", C.POINTER(C.c_int32)), ("n_donors", C.c_int32),
+                ("v0", C.POINTER(C.c_double))]
+
+
+class tbh_scf_report(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double),
+                ("fermi", C.c_double), ("n_cb", C.c_int32), ("n_conv", C.c_int32),
+                ("electrons", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_res", C.c_double),
+                ("lanczos_steps", C.c_int32), ("u_min", C.c_double), ("seconds", C.c_double),
+                ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -93,6 +111,15 @@ _SIGS = [
     ("tbh_lanczos_run", C.c_int, [C.c_void_p, C.POINTER(tbh_lanczos_opts), C.c_void_p,
                                   C.c_void_p, C.c_int32, C.POINTER(tbh_lanczos_report)]),
     ("tbh_tridiag_eig", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("tbh_poisson_solve", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("tbh_scf_create", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_opts), C.POINTER(C.c_void_p)]),
+    ("tbh_scf_destroy", C.c_int, [C.c_void_p]),
+    ("tbh_scf_set_potential", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_scf_get_potential", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_scf_step", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_report)]),
+    ("tbh_scf_run", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(tbh_scf_report)]),
 ]
 
 
@@ -413,3 +440,76 @@ def tridiag_eig(ctx: Context, diag, off):
     _check(lib().tbh_tridiag_eig(ctx.h, d.size, d.ctypes.data, e.ctypes.data if e.size else None,
                                  th.ctypes.data))
     return th
+
+
+def poisson_solve(ctx: Context, grid, h_nm, eps_r, rho, phi=None, rel_tol=1e-10, max_iter=100000):
+    """FP64 CG for -eps0 eps_r Lap_h phi = rho on the device.  rho: [nz, ny, nx]
+    float64 device tensor (e/nm^3); phi: initial guess (updated in place) or
+    None (zero).  Returns (phi, iterations, relative residual)."""
+    import torch
+    if phi is None:
+        phi = torch.zeros_like(rho)
+    g = (C.c_int32 * 3)(*[int(v) for v in grid])
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    rc = lib().tbh_poisson_solve(ctx.h, g, float(h_nm), float(eps_r), C.c_void_p(rho.data_ptr()),
+                                 C.c_void_p(phi.data_ptr()), float(rel_tol), int(max_iter),
+                                 C.byref(it), C.byref(rr))
+    if rc not in (TBH_OK, TBH_ENOCONV):
+        _check(rc)
+    return phi, it.value, rr.value
+
+
+class SCF:
+    """Self-consistent Schrodinger-Poisson loop on a device Hamiltonian."""
+
+    def __init__(self, ham: Hamiltonian, grid, donor_atoms, v0, sigma_mid, e_cbm, h_nm, eps_r=11.7,
+                 T_K=4.0, mix_alpha=0.1, tol_eV=1e-4, n_cand=48, lanczos_iter=600, res_tol=1e-4,
+                 cg_tol=1e-12, cg_max_iter=20000, fermi_fixed=None):
+        self.ham = ham
+        self.grid = tuple(int(g) for g in grid)
+        self._donors = np.ascontiguousarray(donor_atoms, dtype=np.int32)
+        self._v0 = _v0_host(ham, v0)
+        o = tbh_scf_opts((C.c_int32 * 3)(*self.grid), float(h_nm), float(eps_r), float(T_K),
+                         float(mix_alpha), float(tol_eV), float(sigma_mid), float(e_cbm),
+                         float("nan") if fermi_fixed is None else float(fermi_fixed),
+                         int(n_cand), int(lanczos_iter), float(res_tol), float(cg_tol),
+                         int(cg_max_iter), _p(self._donors, C.c_int32), int(self._donors.size),
+                         self._v0.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        _check(lib().tbh_scf_create(ham.h, C.byref(o), C.byref(h)))
+        self.h = h
+
+    def set_potential(self, U=None):
+        """U: [nz, ny, nx] float64 device tensor (eV) or None (zero start)."""
+        _check(lib().tbh_scf_set_potential(self.h, None if U is None else C.c_void_p(U.data_ptr())))
+
+    def potential(self):
+        import torch
+        nx, ny, nz = self.grid
+        U = torch.empty((nz, ny, nx), dtype=torch.float64, device=f"cuda:{self.ham.ctx.device}")
+        _check(lib().tbh_scf_get_potential(self.h, C.c_void_p(U.data_ptr())))
+        return U
+
+    def step(self):
+        r = tbh_scf_report()
+        _check(lib().tbh_scf_step(self.h, C.byref(r)))
+        return {k: getattr(r, k) for k, _ in tbh_scf_report._fields_}
+
+    def run(self, max_iter):
+        r = tbh_scf_report()
+        rc = lib().tbh_scf_run(self.h, int(max_iter), C.byref(r))
+        if rc not in (TBH_OK, TBH_ENOCONV):
+            _check(rc)
+        return {k: getattr(r, k) for k, _ in tbh_scf_report._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tbh_scf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -135,6 +135,7 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         h->n_dangling = M.n_dangling;
         h->nbr_h = M.nbr;
         h->wrap_h = M.wrap;
+        h->pos_h.assign(g->pos_q, g->pos_q + 3 * g->n_atoms);
         // diagonal on-site blocks need no spin-orbit, no passivation
         h->diag = !M.spin && !(M.par.passivation_eV != 0.0 && M.n_dangling > 0);
         const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);

@@ -1,0 +1,526 @@
+// Schrodinger-Poisson self-consistency on the GPU (Sec. III-A):
+// eigenstates (Lanczos) -> charge from filling the states, with the Fermi
+// level from charge neutrality or given -> finite-difference Poisson solved
+// by FP64 conjugate gradients -> the potential updates the Hamiltonian ->
+// repeat until self-consistent.
+//
+// Grid: the a/4 lattice nodes, [nz][ny][nx], periodic in x and y, phi = 0 on
+// the ghost planes z = -1 and z = nz; atom (qx, qy, qz) sits on node
+// (qx, qy, qz).  -eps0 eps_r Lap_h phi = rho; electron potential energy
+// U = -phi (eV).  Donors are +e point charges on their atoms' nodes.
+//
+// The grid (a quarter of a million nodes for the 30,720-atom slab, 2 MB in
+// FP64) lives in the L2/Infinity Cache, so CG is latency-bound: one stencil
+// kernel with the fused p.Ap partial sums, one update kernel with the fused
+// r.r partial sums, and single-block scalar kernels; no host round trip per
+// iteration.
+#include <chrono>
+#include <cmath>
+#include <limits>
+
+#include "lanczos.h"
+#include "scf.h"
+#include "tbh_internal.h"
+
+namespace tbh {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr double EPS0_E_PER_V_NM = 8.8541878128e-12 / 1.602176634e-19 * 1e-9;
+constexpr double KB_EV = 8.617333262e-5;
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// block sum of one double; valid in thread 0
+__device__ double block_sum1(double v) {
+    __shared__ double sh[4];
+    v = warp_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_max1(double v) {
+    __shared__ double sh[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+    return r;
+}
+
+__device__ double block_min1(double v) { return -block_max1(-v); }
+
+__device__ double reduce_part(const double* part, int64_t n) {
+    double v = 0.0;
+    for (int64_t b = threadIdx.x; b < n; b += TPB) v += part[b];
+    return block_sum1(v);
+}
+
+#define GRID_LOOP(i, n) \
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < (n); i += int64_t(gridDim.x) * TPB)
+
+// A p = -Lap_h p; partial sums of p . A p
+__global__ void k_stencil(int nx, int ny, int nz, double inv_h2, const double* __restrict__ p,
+                          double* __restrict__ Ap, double* part, const double* done) {
+    if (done && *done != 0.0) return;
+    const int64_t n = int64_t(nx) * ny * nz;
+    double acc = 0.0;
+    GRID_LOOP(i, n) {
+        const int x = int(i % nx);
+        const int y = int((i / nx) % ny);
+        const int z = int(i / (int64_t(nx) * ny));
+        const double c = p[i];
+        const int64_t row = i - x, plane = i - x - int64_t(y) * nx;
+        double s = p[row + (x + 1 == nx ? 0 : x + 1)] + p[row + (x == 0 ? nx - 1 : x - 1)];
+        s += p[plane + int64_t(y + 1 == ny ? 0 : y + 1) * nx + x] + p[plane + int64_t(y == 0 ? ny - 1 : y - 1) * nx + x];
+        if (z + 1 < nz) s += p[i + int64_t(nx) * ny];
+        if (z > 0) s += p[i - int64_t(nx) * ny];
+        const double a = (6.0 * c - s) * inv_h2;
+        Ap[i] = a;
+        acc += c * a;
+    }
+    if (part) {
+        const double r = block_sum1(acc);
+        if (threadIdx.x == 0) part[blockIdx.x] = r;
+    }
+}
+
+// scalar slots of the CG state
+enum { CG_RR = 0, CG_ALPHA = 1, CG_BETA = 2, CG_DONE = 3, CG_BB = 4, CG_ITERS = 5, CG_REL = 6, CG_NS = 8 };
+
+__global__ void k_cg_alpha(const double* part, int64_t nb, double* s) {
+    if (s[CG_DONE] != 0.0) return;
+    const double pap = reduce_part(part, nb);
+    if (threadIdx.x == 0) s[CG_ALPHA] = pap != 0.0 ? s[CG_RR] / pap : 0.0;
+}
+
+__global__ void k_cg_update(int64_t n, double* x, double* r, const double* p, const double* Ap, double* s,
+                            double* part) {
+    if (s[CG_DONE] != 0.0) return;
+    const double a = s[CG_ALPHA];
+    double acc = 0.0;
+    GRID_LOOP(i, n) {
+        x[i] += a * p[i];
+        const double rv = r[i] - a * Ap[i];
+        r[i] = rv;
+        acc += rv * rv;
+    }
+    const double t = block_sum1(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// beta, convergence; tol is relative to |b|
+__global__ void k_cg_beta(const double* part, int64_t nb, double* s, double rel_tol, int max_iter) {
+    if (s[CG_DONE] != 0.0) return;
+    const double rr = reduce_part(part, nb);
+    if (threadIdx.x != 0) return;
+    s[CG_BETA] = s[CG_RR] != 0.0 ? rr / s[CG_RR] : 0.0;
+    s[CG_RR] = rr;
+    s[CG_ITERS] += 1.0;
+    const double rel = s[CG_BB] > 0.0 ? sqrt(rr / s[CG_BB]) : 0.0;
+    s[CG_REL] = rel;
+    if (rel <= rel_tol || s[CG_ITERS] >= max_iter) s[CG_DONE] = 1.0;
+}
+
+__global__ void k_cg_p(int64_t n, const double* r, double* p, const double* s) {
+    if (s[CG_DONE] != 0.0) return;
+    const double b = s[CG_BETA];
+    GRID_LOOP(i, n) p[i] = r[i] + b * p[i];
+}
+
+// r = b - A x (Ax in r on entry), p = r, partial r.r and b.b
+__global__ void k_cg_init(int64_t n, const double* b, double* r, double* p, double* part) {
+    double rr = 0.0, bb = 0.0;
+    GRID_LOOP(i, n) {
+        const double v = b[i] - r[i];
+        r[i] = v;
+        p[i] = v;
+        rr += v * v;
+        bb += b[i] * b[i];
+    }
+    const double t1 = block_sum1(rr);
+    const double t2 = block_sum1(bb);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = t1;
+        part[2 * blockIdx.x + 1] = t2;
+    }
+}
+
+__global__ void k_cg_init_scalars(const double* part, int64_t nb, double* s, double rel_tol) {
+    double rr = 0.0, bb = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += TPB) {
+        rr += part[2 * b];
+        bb += part[2 * b + 1];
+    }
+    rr = block_sum1(rr);
+    bb = block_sum1(bb);
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < CG_NS; ++k) s[k] = 0.0;
+    s[CG_RR] = rr;
+    s[CG_BB] = bb;
+    const double rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    s[CG_REL] = rel;
+    if (rel <= rel_tol) s[CG_DONE] = 1.0;
+}
+
+__global__ void k_scale(int64_t n, const double* a, double s, double* b) {
+    GRID_LOOP(i, n) b[i] = s * a[i];
+}
+
+// ---------------------------------------------------------------------------
+// charge
+// ---------------------------------------------------------------------------
+
+// partial <psi_c|U|psi_c> over atom blocks: part[c * nb + block]
+__global__ void k_state_pot(const double* Y, int64_t ns, int n_o, int cs, int64_t n_atoms, const double* Ua,
+                            double* part) {
+    const int c = blockIdx.y;
+    const double* y = Y + int64_t(c) * ns;
+    double acc = 0.0;
+    const int per = n_o * cs;
+    GRID_LOOP(i, n_atoms) {
+        double w = 0.0;
+        for (int k = 0; k < per; ++k) {
+            const double v = y[i * per + k];
+            w += v * v;
+        }
+        acc += Ua[i] * w;
+    }
+    const double t = block_sum1(acc);
+    if (threadIdx.x == 0) part[int64_t(c) * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ void k_reduce_rows(const double* part, int64_t nb, double* out) {
+    const int c = blockIdx.x;
+    const double t = reduce_part(part + int64_t(c) * nb, nb);
+    if (threadIdx.x == 0) out[c] = t;
+}
+
+__device__ double fermi(double E, double Ef, double kT) {
+    if (kT <= 0.0) return E < Ef ? 1.0 : (E == Ef ? 0.5 : 0.0);
+    const double t = (E - Ef) / kT;
+    return t > 0 ? exp(-t) / (1.0 + exp(-t)) : 1.0 / (1.0 + exp(t));
+}
+
+// occupations (2 f for counted states, 0 otherwise), E_F, counts.
+// res4 = [ncand][4] (theta, residual, refined, |y|); q = <y|U|y> (unnormalised)
+__global__ void k_fermi(int ncand, const double* res4, const double* q, double res_tol, double sigma_mid,
+                        double n_elec, double kT, double ef_fixed, int use_fixed, double* occ, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int ncb = 0, nconv = 0;
+    double emin = INFINITY, emax = -INFINITY;
+    for (int c = 0; c < ncand; ++c) {
+        const double r = res4[4 * c + 1], E = res4[4 * c + 2], yn = res4[4 * c + 3];
+        const bool conv = r <= res_tol;
+        const bool cb = conv && (E - q[c] / (yn * yn) > sigma_mid);
+        nconv += conv;
+        occ[c] = cb ? 1.0 : -1.0;
+        if (cb) {
+            ++ncb;
+            emin = fmin(emin, E);
+            emax = fmax(emax, E);
+        }
+    }
+    double Ef = ef_fixed;
+    if (!use_fixed && ncb > 0) {
+        double lo = emin - 60 * kT - 1.0, hi = emax + 60 * kT + 1.0;
+        for (int it = 0; it < 400; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            double s = 0.0;
+            for (int c = 0; c < ncand; ++c)
+                if (occ[c] > 0) s += 2.0 * fermi(res4[4 * c + 2], mid, kT);
+            if (s < n_elec) lo = mid; else hi = mid;
+            if (hi - lo < 1e-13) break;
+        }
+        Ef = 0.5 * (lo + hi);
+    }
+    double tot = 0.0;
+    for (int c = 0; c < ncand; ++c) {
+        if (occ[c] > 0) {
+            const double yn = res4[4 * c + 3];
+            occ[c] = 2.0 * fermi(res4[4 * c + 2], Ef, kT) / (yn * yn);
+            tot += 2.0 * fermi(res4[4 * c + 2], Ef, kT);
+        } else {
+            occ[c] = 0.0;
+        }
+    }
+    out[0] = Ef;
+    out[1] = ncb;
+    out[2] = nconv;
+    out[3] = tot;
+}
+
+// electrons per atom n_i = sum_c occ_c sum_alpha |y_c(i, alpha)|^2, then
+// b[node_i] -= n_i / (h^3 eps0 eps_r); b holds the donor term on entry
+__global__ void k_density_rhs(const double* Y, int64_t ns, int ncand, int n_o, int cs, int64_t n_atoms,
+                              const double* occ, const int64_t* node, double scale, double* b, double* n_out) {
+    const int per = n_o * cs;
+    GRID_LOOP(i, n_atoms) {
+        double ni = 0.0;
+        for (int c = 0; c < ncand; ++c) {
+            const double o = occ[c];
+            if (o == 0.0) continue;
+            const double* y = Y + int64_t(c) * ns + i * per;
+            double w = 0.0;
+            for (int k = 0; k < per; ++k) w += y[k] * y[k];
+            ni += o * w;
+        }
+        if (n_out) n_out[i] = ni;
+        b[node[i]] -= ni * scale;
+    }
+}
+
+// U_out = -phi; partial max |U_out - U|; U += alpha (U_out - U); partial min U
+__global__ void k_mix(int64_t n, const double* phi, double* U, double alpha, double* part) {
+    double mx = 0.0, mn = INFINITY;
+    GRID_LOOP(i, n) {
+        const double d = -phi[i] - U[i];
+        mx = fmax(mx, fabs(d));
+        const double u = U[i] + alpha * d;
+        U[i] = u;
+        mn = fmin(mn, u);
+    }
+    const double a = block_max1(mx);
+    const double b = block_min1(mn);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_mix_reduce(const double* part, int64_t nb, double* out) {
+    double mx = 0.0, mn = INFINITY;
+    for (int64_t b = threadIdx.x; b < nb; b += TPB) {
+        mx = fmax(mx, part[2 * b]);
+        mn = fmin(mn, part[2 * b + 1]);
+    }
+    mx = block_max1(mx);
+    mn = block_min1(mn);
+    if (threadIdx.x == 0) {
+        out[0] = mx;
+        out[1] = mn;
+    }
+}
+
+__global__ void k_min(int64_t n, const double* U, double* part) {
+    double mn = INFINITY;
+    GRID_LOOP(i, n) mn = fmin(mn, U[i]);
+    const double b = block_min1(mn);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = 0.0;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void k_gather_atoms(int64_t n_atoms, const int64_t* node, const double* U, double* Ua) {
+    GRID_LOOP(i, n_atoms) Ua[i] = U[node[i]];
+}
+
+int64_t grid_for(int64_t n) {
+    int64_t g = (n + TPB - 1) / TPB;
+    return g < 1 ? 1 : (g > 4096 ? 4096 : g);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Poisson
+// ---------------------------------------------------------------------------
+
+void PoissonWork::ensure(int64_t n) {
+    if (this->n == n && r.p) return;
+    r.alloc(n * 8);
+    p.alloc(n * 8);
+    Ap.alloc(n * 8);
+    part.alloc(2 * 4096 * 8);
+    s.alloc(CG_NS * 8);
+    this->n = n;
+}
+
+void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, const double* b, double* x,
+                double rel_tol, int max_iter, int* iters, double* rel_res) {
+    const int nx = grid[0], ny = grid[1], nz = grid[2];
+    const int64_t n = int64_t(nx) * ny * nz;
+    W.ensure(n);
+    const double inv_h2 = 1.0 / (h * h);
+    const int64_t g = grid_for(n);
+    double* part = W.part.as<double>();
+    double* s = W.s.as<double>();
+    // r = A x (into r), then r = b - r, p = r
+    hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, x, W.r.as<double>(),
+                       (double*)nullptr, (const double*)nullptr);
+    hipLaunchKernelGGL(k_cg_init, dim3(g), dim3(TPB), 0, st, n, b, W.r.as<double>(), W.p.as<double>(), part);
+    hipLaunchKernelGGL(k_cg_init_scalars, dim3(1), dim3(TPB), 0, st, part, g, s, rel_tol);
+    double hs[CG_NS];
+    const int chunk = 25;
+    for (int it = 0; it < max_iter; it += chunk) {
+        for (int k = 0; k < chunk; ++k) {
+            hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, W.p.as<double>(),
+                               W.Ap.as<double>(), part, s + CG_DONE);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(TPB), 0, st, part, g, s);
+            hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, st, n, x, W.r.as<double>(), W.p.as<double>(),
+                               W.Ap.as<double>(), s, part);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(TPB), 0, st, part, g, s, rel_tol, max_iter);
+            hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(TPB), 0, st, n, W.r.as<double>(), W.p.as<double>(), s);
+        }
+        TBH_HIP(hipMemcpyAsync(hs, s, sizeof(hs), hipMemcpyDeviceToHost, st));
+        TBH_HIP(hipStreamSynchronize(st));
+        if (hs[CG_DONE] != 0.0) break;
+    }
+    TBH_HIP(hipGetLastError());
+    if (iters) *iters = int(hs[CG_ITERS]);
+    if (rel_res) *rel_res = hs[CG_REL];
+}
+
+// ---------------------------------------------------------------------------
+// SCF driver
+// ---------------------------------------------------------------------------
+
+Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
+    TBH_REQUIRE(h->has_f64, "the SCF loop needs an FP64 copy of H (build with keep_f64=1)");
+    for (int a = 0; a < 3; ++a) {
+        grid[a] = o.grid[a];
+        TBH_REQUIRE(grid[a] > 0, "grid sizes must be positive");
+    }
+    TBH_REQUIRE(o.h_nm > 0 && o.eps_r > 0 && o.T_K >= 0, "h_nm, eps_r must be positive, T_K >= 0");
+    TBH_REQUIRE(o.mix_alpha > 0 && o.mix_alpha <= 1, "mix_alpha must be in (0, 1]");
+    TBH_REQUIRE(o.n_cand >= 1 && o.lanczos_iter >= o.n_cand, "need n_cand >= 1 and lanczos_iter >= n_cand");
+    TBH_REQUIRE(o.n_donors >= 0 && (o.n_donors == 0 || o.donor_atoms), "bad donor list");
+    TBH_REQUIRE(o.v0, "null start vector");
+    n_nodes = int64_t(grid[0]) * grid[1] * grid[2];
+    // atom -> node
+    std::vector<int64_t> node(h->n);
+    TBH_REQUIRE(!h->pos_h.empty(), "ham has no positions");
+    std::vector<char> seen(n_nodes, 0);
+    for (int64_t i = 0; i < h->n; ++i) {
+        const int32_t* q = &h->pos_h[3 * i];
+        TBH_REQUIRE(q[0] < grid[0] && q[1] < grid[1] && q[2] < grid[2], "atom outside the Poisson grid");
+        node[i] = (int64_t(q[2]) * grid[1] + q[1]) * grid[0] + q[0];
+        seen[node[i]] = 1;
+    }
+    node_d.alloc(h->n * 8);
+    hipStream_t st = h->ctx->stream;
+    TBH_HIP(hipMemcpy(node_d.p, node.data(), h->n * 8, hipMemcpyHostToDevice));
+    // donor term of the right-hand side: +1/(h^3 eps0 eps_r) per donor at its node
+    const double scale = 1.0 / (o.h_nm * o.h_nm * o.h_nm * EPS0_E_PER_V_NM * o.eps_r);
+    std::vector<double> b0(n_nodes, 0.0);
+    for (int d = 0; d < o.n_donors; ++d) {
+        const int32_t a = o.donor_atoms[d];
+        TBH_REQUIRE(a >= 0 && a < h->n, "donor atom index out of range");
+        b0[node[a]] += scale;
+    }
+    b0_d.alloc(n_nodes * 8);
+    TBH_HIP(hipMemcpy(b0_d.p, b0.data(), n_nodes * 8, hipMemcpyHostToDevice));
+    U.alloc(n_nodes * 8);
+    phi.alloc(n_nodes * 8);
+    b.alloc(n_nodes * 8);
+    std::vector<double> z(n_nodes, 0.0);
+    TBH_HIP(hipMemcpy(U.p, z.data(), n_nodes * 8, hipMemcpyHostToDevice));
+    TBH_HIP(hipMemcpy(phi.p, z.data(), n_nodes * 8, hipMemcpyHostToDevice));
+    Ua.alloc(h->n * 8);
+    const size_t ns = size_t(h->dim) * (h->cplx_h ? 2 : 1);
+    v0.alloc(ns * 8);
+    TBH_HIP(hipMemcpy(v0.p, o.v0, ns * 8, hipMemcpyHostToDevice));
+    part.alloc(size_t(std::max<int64_t>(2 * 4096, int64_t(o.n_cand) * 4096)) * 8);
+    occ.alloc(size_t(o.n_cand) * 8);
+    q.alloc(size_t(o.n_cand) * 8);
+    out.alloc(8 * 8);
+    n_atoms_d.alloc(h->n * 8);
+    (void)st;
+}
+
+void Scf::set_potential(const double* Ud) {
+    hipStream_t st = h->ctx->stream;
+    if (Ud)
+        TBH_HIP(hipMemcpyAsync(U.p, Ud, n_nodes * 8, hipMemcpyDeviceToDevice, st));
+    else
+        hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), 0.0,
+                           U.as<double>());
+    // phi guess for the next Poisson solve: -U
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), -1.0,
+                       phi.as<double>());
+    TBH_HIP(hipGetLastError());
+}
+
+void Scf::step(tbh_scf_report& rep) {
+    hipStream_t st = h->ctx->stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t ga = grid_for(h->n), gn = grid_for(n_nodes);
+    double* pt = part.as<double>();
+    // potential on the atoms -> H
+    hipLaunchKernelGGL(k_gather_atoms, dim3(ga), dim3(TPB), 0, st, h->n, node_d.as<int64_t>(), U.as<double>(),
+                       Ua.as<double>());
+    h->pot_d.alloc(size_t(h->n) * 8);
+    TBH_HIP(hipMemcpyAsync(h->pot_d.p, Ua.p, h->n * 8, hipMemcpyDeviceToDevice, st));
+    h->has_pot = true;
+    // Lanczos target: bulk CBM shifted by the deepest potential
+    hipLaunchKernelGGL(k_min, dim3(gn), dim3(TPB), 0, st, n_nodes, U.as<double>(), pt);
+    hipLaunchKernelGGL(k_mix_reduce, dim3(1), dim3(TPB), 0, st, pt, gn, out.as<double>() + 4);
+    double mm[2];
+    TBH_HIP(hipMemcpyAsync(mm, out.as<double>() + 4, 16, hipMemcpyDeviceToHost, st));
+    TBH_HIP(hipStreamSynchronize(st));
+    const double sigma = opt.e_cbm + mm[1];
+    if (!lz) lz = std::make_shared<LzWork>();
+    int steps = 0, brk = 0;
+    lanczos_recurrence(*h, *lz, opt.lanczos_iter, true, v0.as<double>(), nullptr, nullptr, &steps, &brk, nullptr);
+    const int ncand = std::min(opt.n_cand, steps);
+    ritz_pairs(*h, *lz, steps, sigma, ncand, ritz);
+    const auto t1 = std::chrono::steady_clock::now();
+    // charge
+    const size_t ns = size_t(h->dim) * (h->cplx_h ? 2 : 1);
+    const int cs = h->cplx_h ? 2 : 1;
+    dim3 g2(ga, ncand);
+    hipLaunchKernelGGL(k_state_pot, g2, dim3(TPB), 0, st, ritz.Y.as<double>(), int64_t(ns), h->n_o, cs, h->n,
+                       Ua.as<double>(), pt);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(ncand), dim3(TPB), 0, st, pt, ga, q.as<double>());
+    const double kT = KB_EV * opt.T_K;
+    const int use_fixed = std::isnan(opt.fermi_fixed) ? 0 : 1;
+    hipLaunchKernelGGL(k_fermi, dim3(1), dim3(64), 0, st, ncand, ritz.res.as<double>(), q.as<double>(),
+                       opt.res_tol, opt.sigma_mid, double(opt.n_donors), kT, use_fixed ? opt.fermi_fixed : 0.0,
+                       use_fixed, occ.as<double>(), out.as<double>());
+    const double scale = 1.0 / (opt.h_nm * opt.h_nm * opt.h_nm * EPS0_E_PER_V_NM * opt.eps_r);
+    TBH_HIP(hipMemcpyAsync(b.p, b0_d.p, n_nodes * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_density_rhs, dim3(ga), dim3(TPB), 0, st, ritz.Y.as<double>(), int64_t(ns), ncand,
+                       h->n_o, cs, h->n, occ.as<double>(), node_d.as<int64_t>(), scale, b.as<double>(),
+                       n_atoms_d.as<double>());
+    // Poisson (phi holds the previous solution as the guess)
+    int cg_it = 0;
+    double cg_rel = 0.0;
+    poisson_cg(st, pw, grid, opt.h_nm, b.as<double>(), phi.as<double>(), opt.cg_tol, opt.cg_max_iter, &cg_it,
+               &cg_rel);
+    const auto t2 = std::chrono::steady_clock::now();
+    hipLaunchKernelGGL(k_mix, dim3(gn), dim3(TPB), 0, st, n_nodes, phi.as<double>(), U.as<double>(),
+                       opt.mix_alpha, pt);
+    hipLaunchKernelGGL(k_mix_reduce, dim3(1), dim3(TPB), 0, st, pt, gn, out.as<double>() + 4);
+    double o[8];
+    TBH_HIP(hipMemcpyAsync(o, out.p, sizeof(o), hipMemcpyDeviceToHost, st));
+    TBH_HIP(hipStreamSynchronize(st));
+    TBH_HIP(hipGetLastError());
+    ++iterations;
+    rep.iterations = iterations;
+    rep.residual = o[4];
+    rep.converged = o[4] < opt.tol_eV;
+    rep.fermi = o[0];
+    rep.n_cb = int(o[1]);
+    rep.n_conv = int(o[2]);
+    rep.electrons = o[3];
+    rep.cg_iters = cg_it;
+    rep.cg_rel_res = cg_rel;
+    rep.lanczos_steps = steps;
+    rep.u_min = o[5];
+    rep.eig_seconds = std::chrono::duration<double>(t1 - t0).count();
+    rep.poisson_seconds = std::chrono::duration<double>(t2 - t1).count();
+    rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace tbh

@@ -135,6 +135,7 @@ struct Ham {
     bool has_f64 = false, has_pot = false;
     std::vector<int32_t> nbr_h;
     std::vector<int8_t> wrap_h;
+    std::vector<int32_t> pos_h;   // [n][3] positions (a/4 units)
     std::shared_ptr<LzWork> lz;   // Lanczos workspace kept between calls
     int64_t hx_bytes() const;
 };
