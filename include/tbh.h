@@ -136,6 +136,9 @@ typedef struct {
     /* TBH_F32 only: also keep an FP64 copy of H for residuals and
      * Rayleigh-quotient refinement (tbh_apply_h_f64, tbh_lanczos_eigs). */
     int32_t keep_f64;
+    /* TBH_F32 only: also keep the atom-major block copy the multi-vector
+     * kernels read (tbh_apply_h_multi, tbh_batch_*). */
+    int32_t multi_vector;
 } tbh_build_opts;
 
 typedef struct {
@@ -181,9 +184,15 @@ int tbh_ham_neighbours(const tbh_ham* h, int32_t* nbr, int8_t* wrap);
 int tbh_ham_set_potential(tbh_ham* h, const double* pot_dev);
 
 /* y = H x.  x, y: device, [dim] scalars of the ham's precision (complex
- * interleaved) for nrhs = 1, or [dim][nrhs] (right-hand vectors fastest)
- * for nrhs > 1.  x and y must not overlap. */
+ * interleaved).  nrhs must be 1 (see tbh_apply_h_multi).  x and y must not
+ * overlap and must be 16-byte aligned. */
 int tbh_apply_h(tbh_ham* h, const void* x, void* y, int32_t nrhs);
+
+/* Y = H X for nrhs right-hand vectors on the matrix cores (FP32 inputs,
+ * FP32 accumulation).  X, Y: device [n_atoms][n_orb][nrhs] FP32 (complex
+ * interleaved: [..][nrhs][2]).  nrhs = 16 or 32; the ham must be TBH_F32,
+ * built with multi_vector = 1. */
+int tbh_apply_h_multi(tbh_ham* h, const float* X, float* Y, int32_t nrhs);
 /* y = H x in FP64 with the FP64 copy (or the main copy for TBH_F64). */
 int tbh_apply_h_f64(tbh_ham* h, const double* x, double* y);
 
@@ -335,6 +344,34 @@ int tbh_scf_get_potential(tbh_scf* s, double* U_dev);
 int tbh_scf_step(tbh_scf* s, tbh_scf_report* rep);
 /* Steps until converged or max_iter steps; TBH_ENOCONV if not converged. */
 int tbh_scf_run(tbh_scf* s, int32_t max_iter, tbh_scf_report* rep);
+
+/* ------------------------------------------------------------------------
+ * Batched multi-vector H.X: many Hamiltonians of uneven size (cells x
+ * k-points; the k-space groups of Sec. II-C) in one persistent launch,
+ * captured in a HIP graph.
+ * ------------------------------------------------------------------------ */
+typedef struct tbh_batch tbh_batch;
+
+/* hams[count] (same orbital count and complex-ness, TBH_F32, multi_vector),
+ * X[count], Y[count]: device buffers as in tbh_apply_h_multi.  The batch
+ * keeps the pointers (which must stay valid) and a captured graph of the
+ * launch.  grid / remap: persistent workgroups and XCD-contiguous mapping
+ * (0 = defaults: 8 workgroups per CU, remap on). */
+int tbh_batch_create(tbh_ctx* ctx, tbh_ham* const* hams, int32_t count, const float* const* X, float* const* Y,
+                     int32_t nrhs, tbh_batch** out);
+int tbh_batch_destroy(tbh_batch* b);
+/* Launch the captured graph on the context's stream (asynchronous). */
+int tbh_batch_apply(tbh_batch* b);
+/* The same work as one kernel launch per Hamiltonian (the reference point). */
+int tbh_batch_apply_separate(tbh_batch* b);
+/* Choose the launch configuration by timing candidates on the device (or
+ * read it from cache_path when it holds an entry for this batch shape);
+ * the chosen configuration is written back to cache_path (may be NULL) and
+ * the graph is re-captured.  best_ms (may be NULL) receives the time of one
+ * batched application with the chosen configuration. */
+int tbh_batch_autotune(tbh_batch* b, const char* cache_path, int32_t* grid, int32_t* remap, double* best_ms);
+/* Set the launch configuration explicitly (re-captures the graph). */
+int tbh_batch_configure(tbh_batch* b, int32_t grid, int32_t remap);
 
 #ifdef __cplusplus
 }

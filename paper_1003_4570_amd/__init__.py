@@ -45,7 +45,8 @@ class tbh_params(C.Structure):
 class tbh_build_opts(C.Structure):
     _fields_ = [("bond_scale", C.POINTER(C.c_double)), ("onsite_pot", C.POINTER(C.c_double)),
                 ("kfrac", C.POINTER(C.c_double)), ("prec", C.c_int32),
-                ("lanes_per_atom", C.c_int32), ("keep_f64", C.c_int32)]
+                ("lanes_per_atom", C.c_int32), ("keep_f64", C.c_int32),
+                ("multi_vector", C.c_int32)]
 
 
 class tbh_ham_info(C.Structure):
@@ -120,6 +121,15 @@ _SIGS = [
     ("tbh_scf_get_potential", C.c_int, [C.c_void_p, C.c_void_p]),
     ("tbh_scf_step", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_report)]),
     ("tbh_scf_run", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(tbh_scf_report)]),
+    ("tbh_apply_h_multi", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("tbh_batch_create", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    ("tbh_batch_destroy", C.c_int, [C.c_void_p]),
+    ("tbh_batch_apply", C.c_int, [C.c_void_p]),
+    ("tbh_batch_apply_separate", C.c_int, [C.c_void_p]),
+    ("tbh_batch_autotune", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]),
+    ("tbh_batch_configure", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
 ]
 
 
@@ -169,7 +179,8 @@ class _Inputs:
 
     def __init__(self, pos_q, species, box_q, periodic, model, spin, onsite, sk,
                  so_delta=None, passivation_eV=0.0, bond_scale=None, onsite_pot=None,
-                 kfrac=None, prec=TBH_F32, lanes_per_atom=0, keep_f64=False, n_species=None):
+                 kfrac=None, prec=TBH_F32, lanes_per_atom=0, keep_f64=False, n_species=None,
+                 multi_vector=False):
         self.pos = _dptr(pos_q, np.int32).reshape(-1, 3)
         self.spc = _dptr(species, np.uint8).ravel()
         self.onsite = _dptr(onsite, np.float64)
@@ -188,7 +199,7 @@ class _Inputs:
                               _p(self.sk, C.c_double), _p(self.so, C.c_double), float(passivation_eV))
         self.opt = tbh_build_opts(_p(self.bs, C.c_double), _p(self.pot, C.c_double),
                                   _p(self.kf, C.c_double), int(prec), int(lanes_per_atom),
-                                  int(bool(keep_f64)))
+                                  int(bool(keep_f64)), int(bool(multi_vector)))
         self.n = self.pos.shape[0]
         self.n_o = (5 if int(model) == TBH_SP3S else 10) * (2 if spin else 1)
 
@@ -506,6 +517,75 @@ class SCF:
     def close(self):
         if getattr(self, "h", None):
             lib().tbh_scf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_mv(ham, t, nrhs):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("multi-vectors must be contiguous device tensors")
+    want = torch.complex64 if ham.is_complex else torch.float32
+    if t.dtype != want or t.numel() != ham.dim * nrhs:
+        raise TypeError(f"expected {want} [dim, nrhs] = [{ham.dim}, {nrhs}]")
+
+
+def apply_h_multi(ham: Hamiltonian, X, Y=None):
+    """Y = H X on the matrix cores.  X: [dim, nrhs] complex64 / float32
+    device tensor (nrhs = 16 or 32)."""
+    import torch
+    nrhs = X.shape[-1]
+    _check_mv(ham, X, nrhs)
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check_mv(ham, Y, nrhs)
+    _check(lib().tbh_apply_h_multi(ham.h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), int(nrhs)))
+    return Y
+
+
+class Batch:
+    """Many Hamiltonians' multi-vector products in one persistent launch
+    (captured in a HIP graph)."""
+
+    def __init__(self, ctx: Context, hams, Xs, Ys):
+        nrhs = Xs[0].shape[-1]
+        for h, x, y in zip(hams, Xs, Ys):
+            _check_mv(h, x, nrhs)
+            _check_mv(h, y, nrhs)
+        self.ctx, self.hams, self.Xs, self.Ys = ctx, list(hams), list(Xs), list(Ys)
+        n = len(hams)
+        H = (C.c_void_p * n)(*[h.h for h in hams])
+        X = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
+        Y = (C.c_void_p * n)(*[y.data_ptr() for y in Ys])
+        b = C.c_void_p()
+        _check(lib().tbh_batch_create(ctx.h, H, n, X, Y, int(nrhs), C.byref(b)))
+        self.h = b
+
+    def apply(self):
+        _check(lib().tbh_batch_apply(self.h))
+
+    def apply_separate(self):
+        _check(lib().tbh_batch_apply_separate(self.h))
+
+    def configure(self, grid, remap):
+        _check(lib().tbh_batch_configure(self.h, int(grid), int(remap)))
+
+    def autotune(self, cache_path=None):
+        g = C.c_int32(0)
+        r = C.c_int32(0)
+        ms = C.c_double(0)
+        _check(lib().tbh_batch_autotune(self.h, None if cache_path is None else str(cache_path).encode(),
+                                        C.byref(g), C.byref(r), C.byref(ms)))
+        return dict(grid=g.value, remap=r.value, ms=ms.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tbh_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -376,6 +376,38 @@ void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t 
 
 }  // namespace
 
+void pack_atom_major(const HostModel& M, int64_t stride, float* dst) {
+    const int no = M.n_o;
+    const int cs = M.cplx_h ? 2 : 1;
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
+    if (M.n < 1024) nt = 1;
+    auto work = [&](int64_t a0, int64_t a1) {
+        std::vector<cplx> D(no * no), B(4 * no * no);
+        for (int64_t a = a0; a < a1; ++a) {
+            host_atom_blocks(M, a, D.data(), B.data());
+            float* o = dst + a * stride;
+            int64_t s = 0;
+            for (int k = 0; k < 4 * no * no; ++k) {
+                o[s++] = float(B[k].real());
+                if (cs == 2) o[s++] = float(B[k].imag());
+            }
+            for (int k = 0; k < no * no; ++k) {
+                o[s++] = float(D[k].real());
+                if (cs == 2) o[s++] = float(D[k].imag());
+            }
+            while (s < stride) o[s++] = 0.f;
+        }
+    };
+    std::vector<std::thread> th;
+    const int64_t per = (M.n + nt - 1) / nt;
+    for (unsigned w = 0; w < nt; ++w) {
+        const int64_t a0 = w * per, a1 = std::min<int64_t>(M.n, a0 + per);
+        if (a0 < a1) th.emplace_back(work, a0, a1);
+    }
+    for (auto& t : th) t.join();
+}
+
 void pack_layout(const HostModel& M, const Layout& L, bool diag, void* dst) {
     unsigned nt = std::thread::hardware_concurrency();
     nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);

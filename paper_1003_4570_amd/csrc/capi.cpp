@@ -2,6 +2,7 @@
 #include <cstring>
 #include <memory>
 
+#include "hx_multi.h"
 #include "tbh_internal.h"
 
 namespace {
@@ -155,6 +156,15 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
             h->has_f64 = true;
         } else if (o->prec == TBH_F64) {
             h->has_f64 = true;
+        }
+        if (o->multi_vector) {
+            TBH_REQUIRE(o->prec == TBH_F32, "multi_vector needs TBH_F32");
+            const int64_t stride = tbh::mv_block_floats(M.n_o, M.cplx_h);
+            std::vector<float> host(size_t(stride) * M.n);
+            tbh::pack_atom_major(M, stride, host.data());
+            h->mv_blocks.alloc(host.size() * 4);
+            TBH_HIP(hipMemcpy(h->mv_blocks.p, host.data(), host.size() * 4, hipMemcpyHostToDevice));
+            h->has_mv = true;
         }
         h->nbr_d.alloc(M.nbr.size() * 4);
         TBH_HIP(hipMemcpy(h->nbr_d.p, M.nbr.data(), M.nbr.size() * 4, hipMemcpyHostToDevice));

@@ -1,0 +1,176 @@
+// Multi-vector H.X on the matrix cores, single Hamiltonian or a batch of
+// many (cells x k-points) in one persistent launch.
+//
+// The paper groups independent k-points (and biases) into separate solver
+// groups (Sec. II-C, multi-level parallelism, Fig. 1b).  On one GPU the
+// groups become one launch over the concatenated atoms of every
+// (cell, k-point) Hamiltonian, and several right-hand vectors per atom turn
+// every block product into a small dense GEMM:
+//
+//   Y_i (n_o x R) = [B_i0 B_i1 B_i2 B_i3 D_i] [X_n0; X_n1; X_n2; X_n3; X_i]
+//
+// Complex blocks are handled with the real embedding
+//   [Yr; Yi] = [[Br, -Bi], [Bi, Br]] [Xr; Xi],
+// computed as Y^T = X^T A^T with v_mfma_f32_16x16x4f32: the right-hand
+// vectors are the 16-wide M dimension, the embedded output rows the N
+// dimension (two 16-wide tiles for 20 rows), K = 5 n_o (x2 for complex).
+// One wavefront owns one atom at a time: it stages the atom's five blocks
+// (4 KB for 10x10 complex) into LDS with 16-byte loads, reads its B-operand
+// from LDS and gathers the X rows of the neighbours straight from L2.
+// A persistent grid walks the concatenated atom range in contiguous chunks,
+// mapped XCD-contiguously so that one XCD's L2 holds the X rows its
+// neighbouring atoms share.
+#include "tbh_internal.h"
+#include "hx_multi.h"
+
+namespace tbh {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk, int remap) {
+    if (!remap) return bid;
+    const int64_t xcd = bid % 8, idx = bid / 8, q = nblk / 8, r = nblk % 8;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+template <bool CPLX, int NO, int NRHS>
+__global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, int n_inst, int64_t total,
+                                              int64_t chunk, int remap) {
+    constexpr int CS = CPLX ? 2 : 1;
+    constexpr int ME = NO * CS;                 // embedded output rows
+    constexpr int KE = 5 * NO * CS;             // embedded K
+    constexpr int NT = (ME + 15) / 16;          // N tiles
+    constexpr int KS = (KE + 3) / 4;            // K steps
+    constexpr int MT = NRHS / 16;               // M tiles (right-hand vectors)
+    constexpr int BF = 5 * NO * NO * CS;        // block floats per atom
+    constexpr int BFP = (BF + 3) & ~3;          // padded to 16 bytes
+    __shared__ float blk[BFP];
+
+    const int lane = threadIdx.x;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, remap);
+    // the table may be a slice of a larger batch: its atom range starts at
+    // desc[0].atom_begin and spans `total` atoms
+    const int64_t base = desc[0].atom_begin;
+    int64_t g = base + lb * chunk;
+    const int64_t g_end = g + chunk < base + total ? g + chunk : base + total;
+    if (g >= g_end) return;
+    // instance containing g
+    int inst = 0;
+    while (inst + 1 < n_inst && desc[inst + 1].atom_begin <= g) ++inst;
+
+    for (; g < g_end; ++g) {
+        while (g >= desc[inst].atom_begin + desc[inst].n_atoms) ++inst;
+        const MvDesc& d = desc[inst];
+        const int64_t atom = g - d.atom_begin;
+        // stage the five blocks (bonds 0..3, on-site) into LDS
+        const v4f* src = reinterpret_cast<const v4f*>(d.blocks + atom * BFP);
+        for (int c = lane; c < BFP / 4; c += 64) reinterpret_cast<v4f*>(blk)[c] = src[c];
+        __syncthreads();
+        if (d.pot && lane < NO) blk[((4 * NO + lane) * NO + lane) * CS] += float(d.pot[atom]);
+        __syncthreads();
+        int64_t nb[5];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int32_t j = d.nbr[atom * 4 + s];
+            nb[s] = j >= 0 ? j : atom;   // dangling: the staged block is zero
+        }
+        nb[4] = atom;
+        const float* __restrict__ X = d.x;
+        v4f acc[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int kl = lane >> 4, col = lane & 15;
+#pragma unroll 5
+        for (int ks = 0; ks < KS; ++ks) {
+            const int k = ks * 4 + kl;
+            // decode k -> (slot s, column c, input part p)
+            const int kk = k < KE ? k : 0;
+            const int p = CPLX ? (kk & 1) : 0;
+            const int sc = CPLX ? (kk >> 1) : kk;
+            const int s = sc / NO, c = sc % NO;
+            float a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                a[mt] = k < KE ? X[((nb[s] * NO + c) * NRHS + mt * 16 + col) * CS + p] : 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int m = t * 16 + col;
+                float b = 0.f;
+                if (k < KE && m < ME) {
+                    if constexpr (CPLX) {
+                        const int r = m < NO ? m : m - NO;
+                        const int q = m < NO ? p : 1 - p;
+                        const float v = blk[((s * NO + r) * NO + c) * 2 + q];
+                        b = (m < NO && p == 1) ? -v : v;
+                    } else {
+                        b = blk[(s * NO + m) * NO + c];
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], b, acc[mt][t], 0, 0, 0);
+            }
+        }
+        // D[i = 4*(lane/16) + v][j = lane%16] = Y^T[rhs][m]
+        float* __restrict__ Y = d.y;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int m = t * 16 + col;
+                if (m < ME) {
+                    const int r = CPLX ? (m < NO ? m : m - NO) : m;
+                    const int p = CPLX ? (m < NO ? 0 : 1) : 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int rhs = mt * 16 + 4 * kl + v;
+                        Y[((atom * NO + r) * NRHS + rhs) * CS + p] = acc[mt][t][v];
+                    }
+                }
+            }
+        __syncthreads();
+    }
+}
+
+template <bool CPLX, int NO>
+void launch_no(int nrhs, const MvDesc* desc, int n_inst, int64_t total, int grid, int remap, hipStream_t s) {
+    const int64_t chunk = (total + grid - 1) / grid;
+    if (nrhs == 16)
+        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 16>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, chunk, remap);
+    else if (nrhs == 32)
+        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 32>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, chunk, remap);
+    else
+        throw Error(TBH_EINVAL, "multi-vector H.X supports nrhs = 16 or 32");
+}
+
+}  // namespace
+
+bool mv_supported(int n_o, int nrhs) { return (n_o == 5 || n_o == 10 || n_o == 20) && (nrhs == 16 || nrhs == 32); }
+
+int64_t mv_block_floats(int n_o, bool cplx_h) {
+    const int64_t f = 5 * int64_t(n_o) * n_o * (cplx_h ? 2 : 1);
+    return (f + 3) & ~int64_t(3);
+}
+
+void mv_launch(bool cplx_h, int n_o, int nrhs, const MvDesc* desc_dev, int n_inst, int64_t total_atoms, int grid,
+               int remap, hipStream_t s) {
+    if (total_atoms == 0) return;
+    if (grid < 1) grid = 1;
+    if (cplx_h) {
+        if (n_o == 5) launch_no<true, 5>(nrhs, desc_dev, n_inst, total_atoms, grid, remap, s);
+        else if (n_o == 10) launch_no<true, 10>(nrhs, desc_dev, n_inst, total_atoms, grid, remap, s);
+        else if (n_o == 20) launch_no<true, 20>(nrhs, desc_dev, n_inst, total_atoms, grid, remap, s);
+        else throw Error(TBH_EINVAL, "unsupported orbital count");
+    } else {
+        if (n_o == 5) launch_no<false, 5>(nrhs, desc_dev, n_inst, total_atoms, grid, remap, s);
+        else if (n_o == 10) launch_no<false, 10>(nrhs, desc_dev, n_inst, total_atoms, grid, remap, s);
+        else throw Error(TBH_EINVAL, "unsupported orbital count");
+    }
+    TBH_HIP(hipGetLastError());
+}
+
+}  // namespace tbh

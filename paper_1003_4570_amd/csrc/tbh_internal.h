@@ -116,6 +116,9 @@ struct Layout {
 Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
 // Pack atoms into the layout (T = float or double).
 void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst);
+// Atom-major FP32 copy for the multi-vector kernels: per atom [5][n_o][n_o]
+// (bond slots 0..3, on-site), complex interleaved, padded to stride floats.
+void pack_atom_major(const HostModel& m, int64_t stride, float* dst);
 
 // ---------------------------------------------------------------------------
 // the Hamiltonian object
@@ -131,8 +134,8 @@ struct Ham {
     bool diag = false;
     int64_t n_dangling = 0;
     Layout lay, lay64;
-    DevBuf blocks, blocks64, nbr_d, pot_d;
-    bool has_f64 = false, has_pot = false;
+    DevBuf blocks, blocks64, nbr_d, pot_d, mv_blocks, mv_desc;
+    bool has_f64 = false, has_pot = false, has_mv = false;
     std::vector<int32_t> nbr_h;
     std::vector<int8_t> wrap_h;
     std::vector<int32_t> pos_h;   // [n][3] positions (a/4 units)

@@ -41,8 +41,6 @@ def test_poisson_cg_vs_spectral(ctx, shape):
 def test_poisson_nonconvergence_reported(ctx):
     import torch
     rho = torch.ones((40, 16, 16), dtype=torch.float64, device="cuda")
-    with pytest.raises(AssertionError):
-        raise AssertionError
     phi, it, rr = tbh.poisson_solve(ctx, (16, 16, 40), W.H_GRID_NM, 11.7, rho, rel_tol=1e-14, max_iter=3)
     assert it == 3 and rr > 1e-14
 
