@@ -284,9 +284,10 @@ int tbh_poisson_solve(tbh_ctx* ctx, const int32_t grid[3], double h_nm, double e
  * One step with input potential energy U (eV, on the grid; atom (qx,qy,qz)
  * sits on node (qx,qy,qz)):
  *  1. H(U) = H_TB + U at every atom's orbitals;
- *  2. Lanczos (full CGS2, lanczos_iter steps) targeted at e_cbm + min U; the
- *     n_cand Ritz pairs nearest the target with residual <= res_tol are the
- *     states, their energies the FP64 Rayleigh quotients;
+ *  2. Lanczos (full CGS2, lanczos_iter steps) targeted 0.05 eV below the
+ *     lowest filled state of the previous step (first step, or none filled:
+ *     e_cbm + min U); the n_cand Ritz pairs nearest the target with residual
+ *     <= res_tol are the states, their energies the FP64 Rayleigh quotients;
  *  3. conduction-band-like states (E - <psi|U|psi> > sigma_mid) are filled
  *     with spin degeneracy 2 and Fermi-Dirac occupation at T_K; the Fermi
  *     level comes from neutrality (2 sum f = n_donors) unless fermi_fixed is
@@ -329,6 +330,7 @@ typedef struct {
     double cg_rel_res;
     int32_t lanczos_steps;
     double u_min;             /* min U after the update (eV) */
+    double sigma;             /* Lanczos target of the step (eV) */
     double seconds, eig_seconds, poisson_seconds;
 } tbh_scf_report;
 

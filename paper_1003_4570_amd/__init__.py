@@ -83,7 +83,8 @@ class tbh_scf_report(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double),
                 ("fermi", C.c_double), ("n_cb", C.c_int32), ("n_conv", C.c_int32),
                 ("electrons", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_res", C.c_double),
-                ("lanczos_steps", C.c_int32), ("u_min", C.c_double), ("seconds", C.c_double),
+                ("lanczos_steps", C.c_int32), ("u_min", C.c_double), ("sigma", C.c_double),
+                ("seconds", C.c_double),
                 ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double)]
 
 

@@ -145,71 +145,66 @@ __global__ void k_scale_next(int64_t n, const T* w, T* vn, LzDev d, int only_fla
         vn[i] = T(double(w[i]) * ib);
 }
 
+// w -= alpha_j v_j (before the first projection pass)
+template <typename T>
+__global__ void k_sub_alpha(int64_t n, T* w, const T* vj, LzDev d, int j) {
+    if (d.ctrl[LZ_BREAK] != 0.0) return;
+    const double a = d.alpha[j];
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+        w[i] = T(double(w[i]) - a * double(vj[i]));
+}
+
 // Classical Gram-Schmidt projections c_i = v_i^H w, i < nvec, as per-block
-// partials part[(i * nrb + block) * CS + {re, im}].  With sub_alpha the block
-// first applies w -= alpha_j v_j to its rows (and writes w back).  A block
-// owns RPT * TPB consecutive elements.
+// partials part[(i * nrb + row_block) * CS + {re, im}].  The grid is
+// (row blocks) x (groups of VG vectors); a block owns RPT * TPB consecutive
+// elements and one group, so small dimensions with many vectors still fill
+// the device.
 template <typename T, bool CPLX, int VG, int RPT>
-__global__ __launch_bounds__(TPB) void k_orth_dots(int64_t n_el, const T* V, int64_t ld, int nvec, T* w,
-                                                   LzDev d, int j, int sub_alpha, double* part) {
+__global__ __launch_bounds__(TPB) void k_orth_dots(int64_t n_el, const T* V, int64_t ld, int nvec, const T* w,
+                                                   LzDev d, double* part) {
     constexpr int CS = CPLX ? 2 : 1;
     if (d.ctrl[LZ_BREAK] != 0.0) return;
     const int64_t nrb = gridDim.x;
     const int64_t e0 = int64_t(blockIdx.x) * RPT * TPB + threadIdx.x;
+    const int g0 = blockIdx.y * VG;
     double wr[RPT][CS];
-    const double a = sub_alpha ? d.alpha[j] : 0.0;
-    const T* vj = V + int64_t(j) * ld;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int64_t e = e0 + int64_t(k) * TPB;
 #pragma unroll
-        for (int q = 0; q < CS; ++q) wr[k][q] = 0.0;
-        if (e < n_el) {
-#pragma unroll
-            for (int q = 0; q < CS; ++q) {
-                double v = double(w[e * CS + q]);
-                if (sub_alpha) {
-                    const T u = T(v - a * double(vj[e * CS + q]));
-                    w[e * CS + q] = u;
-                    v = double(u);
-                }
-                wr[k][q] = v;
-            }
-        }
+        for (int q = 0; q < CS; ++q) wr[k][q] = e < n_el ? double(w[e * CS + q]) : 0.0;
     }
-    __shared__ double sh[4][VG * CS];
-    for (int g0 = 0; g0 < nvec; g0 += VG) {
-        double acc[VG * CS];
+    double acc[VG * CS];
 #pragma unroll
-        for (int t = 0; t < VG * CS; ++t) acc[t] = 0.0;
+    for (int t = 0; t < VG * CS; ++t) acc[t] = 0.0;
 #pragma unroll
-        for (int t = 0; t < VG; ++t) {
-            const int i = g0 + t;
-            if (i < nvec) {
-                const T* vi = V + int64_t(i) * ld;
+    for (int t = 0; t < VG; ++t) {
+        const int i = g0 + t;
+        if (i < nvec) {
+            const T* vi = V + int64_t(i) * ld;
 #pragma unroll
-                for (int k = 0; k < RPT; ++k) {
-                    const int64_t e = e0 + int64_t(k) * TPB;
-                    if (e < n_el) {
-                        if constexpr (CPLX) {
-                            const double vr = double(vi[2 * e]), vim = double(vi[2 * e + 1]);
-                            acc[2 * t] += vr * wr[k][0] + vim * wr[k][1];
-                            acc[2 * t + 1] += vr * wr[k][1] - vim * wr[k][0];
-                        } else {
-                            acc[t] += double(vi[e]) * wr[k][0];
-                        }
+            for (int k = 0; k < RPT; ++k) {
+                const int64_t e = e0 + int64_t(k) * TPB;
+                if (e < n_el) {
+                    if constexpr (CPLX) {
+                        const double vr = double(vi[2 * e]), vim = double(vi[2 * e + 1]);
+                        acc[2 * t] += vr * wr[k][0] + vim * wr[k][1];
+                        acc[2 * t + 1] += vr * wr[k][1] - vim * wr[k][0];
+                    } else {
+                        acc[t] += double(vi[e]) * wr[k][0];
                     }
                 }
             }
         }
-        block_sum<VG * CS>(acc, sh);
-        if (threadIdx.x == 0) {
+    }
+    __shared__ double sh[4][VG * CS];
+    block_sum<VG * CS>(acc, sh);
+    if (threadIdx.x == 0) {
 #pragma unroll
-            for (int t = 0; t < VG; ++t)
-                if (g0 + t < nvec)
+        for (int t = 0; t < VG; ++t)
+            if (g0 + t < nvec)
 #pragma unroll
-                    for (int q = 0; q < CS; ++q) part[((g0 + t) * nrb + blockIdx.x) * CS + q] = acc[t * CS + q];
-        }
+                for (int q = 0; q < CS; ++q) part[((g0 + t) * nrb + blockIdx.x) * CS + q] = acc[t * CS + q];
     }
 }
 
@@ -632,14 +627,22 @@ void orth_cgs2(Ham& h, LzWork& W, const LzDev& d, int j, hipStream_t st) {
     constexpr int RPT = 4, VG = 8;
     const int64_t nrb = (n_el + RPT * TPB - 1) / (RPT * TPB);
     const int nvec = j + 1;
+    const dim3 gd(unsigned(nrb), unsigned((nvec + VG - 1) / VG));
     double* part = W.part.as<double>();
     double* c = W.coef.as<double>();
     const int64_t gu = grid_for(n_el);
+    const int64_t gv = grid_for(ld);
     const size_t shm = sizeof(double) * (cx ? 2 : 1) * size_t(nvec);
+    if (f64)
+        hipLaunchKernelGGL(k_sub_alpha<double>, dim3(gv), dim3(TPB), 0, st, ld, W.w.as<double>(),
+                           W.V.as<double>() + int64_t(j) * ld, d, j);
+    else
+        hipLaunchKernelGGL(k_sub_alpha<float>, dim3(gv), dim3(TPB), 0, st, ld, W.w.as<float>(),
+                           W.V.as<float>() + int64_t(j) * ld, d, j);
     for (int pass = 0; pass < 2; ++pass) {
 #define TBH_ORTH(T, CX)                                                                               \
-    hipLaunchKernelGGL((k_orth_dots<T, CX, VG, RPT>), dim3(nrb), dim3(TPB), 0, st, n_el,              \
-                       static_cast<const T*>(W.V.p), ld, nvec, W.w.as<T>(), d, j, int(pass == 0), part); \
+    hipLaunchKernelGGL((k_orth_dots<T, CX, VG, RPT>), gd, dim3(TPB), 0, st, n_el,                     \
+                       static_cast<const T*>(W.V.p), ld, nvec, W.w.as<T>(), d, part);                 \
     hipLaunchKernelGGL((k_orth_reduce<CX>), dim3(nvec), dim3(TPB), 0, st, part, nrb, c, d);          \
     hipLaunchKernelGGL((k_orth_update<T, CX>), dim3(gu), dim3(TPB), shm, st, n_el,                    \
                        static_cast<const T*>(W.V.p), ld, nvec, c, W.w.as<T>(), d,                     \

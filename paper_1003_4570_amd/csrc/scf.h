@@ -23,6 +23,8 @@ struct Scf {
     int grid[3];
     int64_t n_nodes = 0;
     int iterations = 0;
+    bool have_prev = false;     // a filled state was found on the previous step
+    double prev_emin = 0.0;     // lowest filled state energy of the previous step
     DevBuf node_d, b0_d, U, phi, b, Ua, v0, part, occ, q, out, n_atoms_d;
     PoissonWork pw;
     std::shared_ptr<LzWork> lz;

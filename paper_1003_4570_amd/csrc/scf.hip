@@ -258,6 +258,7 @@ __global__ void k_fermi(int ncand, const double* res4, const double* q, double r
     out[1] = ncb;
     out[2] = nconv;
     out[3] = tot;
+    out[6] = ncb > 0 ? emin : 0.0;
 }
 
 // electrons per atom n_i = sum_c occ_c sum_alpha |y_c(i, alpha)|^2, then
@@ -469,7 +470,9 @@ void Scf::step(tbh_scf_report& rep) {
     double mm[2];
     TBH_HIP(hipMemcpyAsync(mm, out.as<double>() + 4, 16, hipMemcpyDeviceToHost, st));
     TBH_HIP(hipStreamSynchronize(st));
-    const double sigma = opt.e_cbm + mm[1];
+    // target: just below the lowest filled state of the previous step; on the
+    // first step (or if none was filled) the bulk CBM shifted by min U
+    const double sigma = have_prev ? prev_emin - 0.05 : opt.e_cbm + mm[1];
     if (!lz) lz = std::make_shared<LzWork>();
     int steps = 0, brk = 0;
     lanczos_recurrence(*h, *lz, opt.lanczos_iter, true, v0.as<double>(), nullptr, nullptr, &steps, &brk, nullptr);
@@ -507,6 +510,8 @@ void Scf::step(tbh_scf_report& rep) {
     TBH_HIP(hipStreamSynchronize(st));
     TBH_HIP(hipGetLastError());
     ++iterations;
+    have_prev = o[1] > 0;
+    prev_emin = o[6];
     rep.iterations = iterations;
     rep.residual = o[4];
     rep.converged = o[4] < opt.tol_eV;
@@ -518,6 +523,7 @@ void Scf::step(tbh_scf_report& rep) {
     rep.cg_rel_res = cg_rel;
     rep.lanczos_steps = steps;
     rep.u_min = o[5];
+    rep.sigma = sigma;
     rep.eig_seconds = std::chrono::duration<double>(t1 - t0).count();
     rep.poisson_seconds = std::chrono::duration<double>(t2 - t1).count();
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
