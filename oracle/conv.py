@@ -1,0 +1,123 @@
+"""Oracle: the 3-D convolutional surrogate of the initial potential.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper's self-consistent loop starts from some potential and iterates
+(Sec. III-A); the surrogate proposes that start from the donor map.  The
+network is fixed here by its definition: four 3x3x3 convolutions
+1 -> C -> C -> C -> 1 with dilations (1, 2, 4, 1), ReLU after the first three,
+circular padding along x and y (the slab is periodic there) and zero padding
+along z.  Tensors are [channels, nz, ny, nx]; weights [c_out, c_in, 3, 3, 3]
+indexed [dz][dy][dx] with tap offset (d - 1) * dilation.
+
+forward() optionally rounds every layer's output to FP16 (half_acts=True),
+the storage precision of the activations; arithmetic is FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DILATIONS = (1, 2, 4, 1)
+
+
+def shifted(x, oz, oy, ox):
+    """s[c, z, y, x] = x[c, z + oz, (y + oy) % ny, (x + ox) % nx], zero when
+    z + oz is outside [0, nz)."""
+    s = np.roll(x, shift=(-oy, -ox), axis=(2, 3))
+    out = np.zeros_like(s)
+    nz = x.shape[1]
+    if oz >= 0:
+        out[:, : nz - oz] = s[:, oz:]
+    else:
+        out[:, -oz:] = s[:, : nz + oz]
+    return out
+
+
+def conv3d(x, W, b, dil):
+    """y[o] = b[o] + sum_{c, taps} W[o, c, t] * x[c] shifted by the tap."""
+    y = np.zeros((W.shape[0],) + x.shape[1:]) + b[:, None, None, None]
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                xs = shifted(x, (dz - 1) * dil, (dy - 1) * dil, (dx - 1) * dil)
+                y += np.einsum("oc,czyx->ozyx", W[:, :, dz, dy, dx], xs)
+    return y
+
+
+def conv3d_backward(x, W, dil, dy):
+    """Gradients of sum(dy * conv3d(x, W, b)) w.r.t. x, W and b."""
+    dx = np.zeros_like(x, dtype=np.float64)
+    dW = np.zeros_like(W, dtype=np.float64)
+    for dz in range(3):
+        for dyy in range(3):
+            for dxx in range(3):
+                oz, oy, ox = (dz - 1) * dil, (dyy - 1) * dil, (dxx - 1) * dil
+                xs = shifted(x, oz, oy, ox)
+                dW[:, :, dz, dyy, dxx] = np.einsum("ozyx,czyx->oc", dy, xs)
+                # adjoint of the shift: shift back by the opposite offset
+                dx += shifted(np.einsum("oc,ozyx->czyx", W[:, :, dz, dyy, dxx], dy), -oz, -oy, -ox)
+    db = dy.sum(axis=(1, 2, 3))
+    return dx, dW, db
+
+
+def init_params(rng, channels=32, scale=None):
+    """He-style random init for the four layers (FP32-representable)."""
+    shapes = [(channels, 1), (channels, channels), (channels, channels), (1, channels)]
+    params = []
+    for co, ci in shapes:
+        std = np.sqrt(2.0 / (27 * ci)) if scale is None else scale
+        W = (rng.standard_normal((co, ci, 3, 3, 3)) * std).astype(np.float32).astype(np.float64)
+        b = np.zeros(co)
+        params.append((W, b))
+    return params
+
+
+def _half(a):
+    return a.astype(np.float16).astype(np.float64)
+
+
+def forward(x, params, half_acts=False, half_weights=False):
+    """Network output [1, nz, ny, nx] and the cache for backward."""
+    acts = [x]
+    pres = []
+    h = x
+    for li, ((W, b), dil) in enumerate(zip(params, DILATIONS)):
+        Wl = _half(W) if half_weights else W
+        bl = _half(b) if half_weights else b
+        pre = conv3d(h, Wl, bl, dil)
+        pres.append(pre)
+        h = np.maximum(pre, 0.0) if li < 3 else pre
+        if half_acts and li < 3:
+            h = _half(h)
+        acts.append(h)
+    return h, dict(acts=acts, pres=pres)
+
+
+def backward(params, cache, dout, half_weights=False):
+    """Gradients [(dW, db)] for dout = d loss / d output."""
+    grads = [None] * 4
+    g = dout
+    for li in range(3, -1, -1):
+        W, b = params[li]
+        Wl = _half(W) if half_weights else W
+        if li < 3:
+            g = g * (cache["pres"][li] > 0)
+        dx, dW, db = conv3d_backward(cache["acts"][li], Wl, DILATIONS[li], g)
+        grads[li] = (dW, db)
+        g = dx
+    return grads
+
+
+def mse(pred, target):
+    """mean((pred - target)^2) and its gradient."""
+    d = pred - target
+    return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba), t counted from 1.  Returns (w, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
