@@ -131,6 +131,15 @@ _SIGS = [
     ("tbh_batch_autotune", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]),
     ("tbh_batch_configure", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("tbh_net_create", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]),
+    ("tbh_net_destroy", C.c_int, [C.c_void_p]),
+    ("tbh_net_num_params", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("tbh_net_set_params", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_net_get_params", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_net_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("tbh_net_gradients", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    ("tbh_net_train_step", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32,
+                                     C.c_double, C.POINTER(C.c_double)]),
 ]
 
 
@@ -594,3 +603,92 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The convolutional start-potential surrogate (device kernels).
+    grid = (nx, ny, nz); maps are float32 device tensors [nz, ny, nx]."""
+
+    def __init__(self, ctx: Context, grid, channels=32):
+        self.ctx = ctx
+        self.grid = tuple(int(g) for g in grid)
+        h = C.c_void_p()
+        _check(lib().tbh_net_create(ctx.h, int(channels), (C.c_int32 * 3)(*self.grid), C.byref(h)))
+        self.h = h
+        n = C.c_int64(0)
+        _check(lib().tbh_net_num_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def set_params(self, flat):
+        w = np.ascontiguousarray(flat, dtype=np.float32).ravel()
+        assert w.size == self.n_params
+        _check(lib().tbh_net_set_params(self.h, w.ctypes.data))
+
+    def get_params(self):
+        w = np.empty(self.n_params, np.float32)
+        _check(lib().tbh_net_get_params(self.h, w.ctypes.data))
+        return w
+
+    def _chk(self, t):
+        import torch
+        nx, ny, nz = self.grid
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+                and t.is_contiguous() and t.numel() == nx * ny * nz):
+            raise TypeError("maps must be contiguous float32 device tensors [nz, ny, nx]")
+
+    def forward(self, x, y=None):
+        import torch
+        self._chk(x)
+        if y is None:
+            y = torch.empty_like(x)
+        self._chk(y)
+        _check(lib().tbh_net_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def gradients(self, x, t):
+        self._chk(x)
+        self._chk(t)
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_double(0)
+        _check(lib().tbh_net_gradients(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                       g.ctypes.data, C.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, xs, ts, lr=1e-3):
+        for a in list(xs) + list(ts):
+            self._chk(a)
+        n = len(xs)
+        X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        T = (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        loss = C.c_double(0)
+        _check(lib().tbh_net_train_step(self.h, X, T, n, float(lr), C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tbh_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def flatten_params(params):
+    """Canonical flat parameter vector from [(W [co, ci, 3, 3, 3], b [co])]."""
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
+
+
+def unflatten_params(flat, channels=32):
+    shapes = [(channels, 1), (channels, channels), (channels, channels), (1, channels)]
+    out, o = [], 0
+    for co, ci in shapes:
+        nW = co * ci * 27
+        W = np.asarray(flat[o:o + nW], dtype=np.float64).reshape(co, ci, 3, 3, 3)
+        o += nW
+        b = np.asarray(flat[o:o + co], dtype=np.float64)
+        o += co
+        out.append((W, b))
+    return out

@@ -1,0 +1,369 @@
+// 3-D convolutional surrogate of the self-consistent potential: inference
+// and training kernels.
+//
+// The self-consistent loop of the paper (Sec. III-A) iterates from a start
+// potential; this network maps the donor-count map to a start potential.
+// Four 3x3x3 convolutions 1 -> C -> C -> C -> 1 with dilations (1, 2, 4, 1),
+// ReLU after the first three, circular padding along x and y, zero padding
+// along z.  Activations are FP16, channels-last [voxel][channel]; weights are
+// FP32 masters with FP16 copies, laid out [c_out][tap][c_in] with
+// tap = dz*9 + dy*3 + dx (offset (d-1)*dilation).
+//
+// Forward and backward-data are implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x16f16, FP32 accumulation): M = 16 voxels per wavefront,
+// N = output channels, K = 27 taps x input channels, the A operand gathered
+// straight from the shifted voxels (8-byte loads of 4 channels), the B
+// operand from the FP16 weights.  Backward-data is the forward convolution
+// of the upstream gradient with tap-reversed, channel-transposed weights,
+// with the previous layer's ReLU mask applied in the epilogue.  The weight
+// gradient is an FP32 reduction over voxels in fixed order.  The loss
+// gradient is scaled by the voxel count (sum of squares) so FP16 gradients
+// stay in range; the optimizer divides it back out.
+#include <cmath>
+
+#include "conv.h"
+#include "tbh_internal.h"
+
+namespace tbh {
+
+namespace {
+
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int TPB = 256;
+
+struct Geo {
+    int nx, ny, nz;
+    int64_t nvox;
+};
+
+__device__ __forceinline__ int64_t shifted_voxel(const Geo g, int64_t v, int tap, int dil) {
+    const int x = int(v % g.nx);
+    const int y = int((v / g.nx) % g.ny);
+    const int z = int(v / (int64_t(g.nx) * g.ny));
+    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+    const int zz = z + (dz - 1) * dil;
+    if (zz < 0 || zz >= g.nz) return -1;
+    int yy = (y + (dy - 1) * dil) % g.ny;
+    if (yy < 0) yy += g.ny;
+    int xx = (x + (dx - 1) * dil) % g.nx;
+    if (xx < 0) xx += g.nx;
+    return (int64_t(zz) * g.ny + yy) * g.nx + xx;
+}
+
+// out[v][co] = act(b[co] + sum_{t, ci} W[co][t][ci] in[shift_t(v)][ci])
+// MODE 0: ReLU, FP16 out; 1: identity, FP32 out; 2: identity times the mask
+// (mask[v][co] > 0), FP16 out (backward-data).
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(TPB) void k_conv(Geo g, int dil, const _Float16* __restrict__ in,
+                                              const _Float16* __restrict__ W, const _Float16* __restrict__ bias,
+                                              const _Float16* __restrict__ mask, void* out) {
+    constexpr int K = 27 * CIN;
+    constexpr int KS = (K + 15) / 16;
+    constexpr int NT = (COUT + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t v0 = (int64_t(blockIdx.x) * 4 + wave) * 16;
+    if (v0 >= g.nvox) return;
+    const int row = lane & 15, kq = lane >> 4;
+    const int64_t v = v0 + row;
+    const bool vin = v < g.nvox;
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k0 = ks * 16 + kq * 4;
+        h4 a;
+        if constexpr (CIN % 4 == 0) {
+            const int tap = k0 / CIN, ci = k0 % CIN;
+            const int64_t s = vin ? shifted_voxel(g, v, tap, dil) : -1;
+            if (s >= 0) a = *reinterpret_cast<const h4*>(in + s * CIN + ci);
+            else a = h4{0, 0, 0, 0};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + e;
+                _Float16 val = 0;
+                if (k < K && vin) {
+                    const int tap = k / CIN, ci = k % CIN;
+                    const int64_t s = shifted_voxel(g, v, tap, dil);
+                    if (s >= 0) val = in[s * CIN + ci];
+                }
+                a[e] = val;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + row;
+            h4 b;
+            if constexpr (K % 4 == 0) {
+                if (co < COUT && k0 < K) b = *reinterpret_cast<const h4*>(W + int64_t(co) * K + k0);
+                else b = h4{0, 0, 0, 0};
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) b[e] = (co < COUT && k0 + e < K) ? W[int64_t(co) * K + k0 + e] : _Float16(0);
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    // D[i = 4*(lane/16) + r][j = lane%16]: voxel v0 + i, channel t*16 + j
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + row;
+        if (co >= COUT) continue;
+        const float bb = bias ? float(bias[co]) : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t vo = v0 + kq * 4 + r;
+            if (vo >= g.nvox) continue;
+            float val = acc[t][r] + bb;
+            if constexpr (MODE == 0) {
+                val = val > 0.f ? val : 0.f;
+                static_cast<_Float16*>(out)[vo * COUT + co] = _Float16(val);
+            } else if constexpr (MODE == 1) {
+                static_cast<float*>(out)[vo * COUT + co] = val;
+            } else {
+                if (!(float(mask[vo * COUT + co]) > 0.f)) val = 0.f;
+                static_cast<_Float16*>(out)[vo * COUT + co] = _Float16(val);
+            }
+        }
+    }
+}
+
+// partial weight gradients: part[chunk][w], w = (co, tap, ci) (+ COUT bias
+// entries at the end), over the chunk's voxels
+template <int CIN, int COUT>
+__global__ void k_conv_wgrad(Geo g, int dil, const _Float16* __restrict__ in, const _Float16* __restrict__ dout,
+                             int64_t chunk, float* part) {
+    constexpr int NW = COUT * 27 * CIN;
+    const int w = blockIdx.x * TPB + threadIdx.x;
+    if (w >= NW + COUT) return;
+    const int64_t c0 = int64_t(blockIdx.y) * chunk;
+    const int64_t c1 = c0 + chunk < g.nvox ? c0 + chunk : g.nvox;
+    float acc = 0.f;
+    if (w < NW) {
+        const int co = w / (27 * CIN), rem = w % (27 * CIN), tap = rem / CIN, ci = rem % CIN;
+        for (int64_t v = c0; v < c1; ++v) {
+            const int64_t s = shifted_voxel(g, v, tap, dil);
+            if (s >= 0) acc += float(dout[v * COUT + co]) * float(in[s * CIN + ci]);
+        }
+    } else {
+        const int co = w - NW;
+        for (int64_t v = c0; v < c1; ++v) acc += float(dout[v * COUT + co]);
+    }
+    part[int64_t(blockIdx.y) * (NW + COUT) + w] = acc;
+}
+
+// grad[w] += sum over chunks (fixed order)
+__global__ void k_reduce_chunks(const float* part, int nchunk, int nw, float* grad) {
+    const int w = blockIdx.x * TPB + threadIdx.x;
+    if (w >= nw) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * nw + w];
+    grad[w] += float(s);
+}
+
+// pred FP32, target FP32: partial sum of squares, dout = 2 (pred - target) in FP16
+__global__ void k_mse(int64_t n, const float* pred, const float* target, _Float16* dout, double* part) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+        const float d = pred[i] - target[i];
+        dout[i] = _Float16(2.f * d);
+        acc += double(d) * double(d);
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void k_sum_part(const double* part, int n, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s;
+    }
+}
+
+__global__ void k_f32_to_f16(int64_t n, const float* a, _Float16* b) {
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+        b[i] = _Float16(a[i]);
+}
+
+// W'[ci][t][co] = W[co][26 - t][ci] (backward-data weights)
+__global__ void k_flip_weights(int cout, int cin, const _Float16* W, _Float16* Wt) {
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= cout * 27 * cin) return;
+    const int co = i / (27 * cin), rem = i % (27 * cin), t = rem / cin, ci = rem % cin;
+    Wt[(int64_t(ci) * 27 + (26 - t)) * cout + co] = W[i];
+}
+
+// Adam on FP32 masters: g = grad * gscale; updates w, m, v and the FP16 copy
+__global__ void k_adam(int64_t n, float* w, float* m, float* v, const float* grad, _Float16* wh, float gscale,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+        const float g = grad[i] * gscale;
+        const float mi = b1 * m[i] + (1.f - b1) * g;
+        const float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        wh[i] = _Float16(wi);
+    }
+}
+
+__global__ void k_fill_f32(int64_t n, float* a, float val) {
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) a[i] = val;
+}
+
+int64_t gfor(int64_t n) {
+    int64_t g = (n + TPB - 1) / TPB;
+    return g < 1 ? 1 : (g > 4096 ? 4096 : g);
+}
+
+template <int CIN, int COUT, int MODE>
+void conv_launch(const Geo& g, int dil, const _Float16* in, const _Float16* W, const _Float16* b,
+                 const _Float16* mask, void* out, hipStream_t s) {
+    const int64_t tiles = (g.nvox + 15) / 16;
+    const int64_t blocks = (tiles + 3) / 4;
+    hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), dim3(blocks), dim3(TPB), 0, s, g, dil, in, W, b, mask, out);
+}
+
+template <int CIN, int COUT>
+void wgrad_launch(const Geo& g, int dil, const _Float16* in, const _Float16* dout, float* part, int nchunk,
+                  float* grad, hipStream_t s) {
+    constexpr int NW = COUT * 27 * CIN + COUT;
+    const int64_t chunk = (g.nvox + nchunk - 1) / nchunk;
+    dim3 grid((NW + TPB - 1) / TPB, nchunk);
+    hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), grid, dim3(TPB), 0, s, g, dil, in, dout, chunk, part);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((NW + TPB - 1) / TPB), dim3(TPB), 0, s, part, nchunk, NW, grad);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Net
+// ---------------------------------------------------------------------------
+
+static const int kDil[4] = {1, 2, 4, 1};
+
+Net::Net(Ctx* c, int channels, const int grid[3]) : ctx(c), C(channels) {
+    TBH_REQUIRE(channels == 32, "the surrogate kernels are built for 32 channels");
+    for (int a = 0; a < 3; ++a) {
+        TBH_REQUIRE(grid[a] > 0, "grid sizes must be positive");
+        g[a] = grid[a];
+    }
+    nvox = int64_t(g[0]) * g[1] * g[2];
+    const int cin[4] = {1, C, C, C}, cout[4] = {C, C, C, 1};
+    n_params = 0;
+    for (int l = 0; l < 4; ++l) {
+        off_w[l] = n_params;
+        n_params += int64_t(cout[l]) * 27 * cin[l];
+        off_b[l] = n_params;
+        n_params += cout[l];
+        lin[l] = cin[l];
+        lout[l] = cout[l];
+    }
+    w32.alloc(n_params * 4);
+    m32.alloc(n_params * 4);
+    v32.alloc(n_params * 4);
+    grad.alloc(n_params * 4);
+    w16.alloc(n_params * 2);
+    wt16.alloc(n_params * 2);
+    for (int l = 0; l < 4; ++l) act[l].alloc(size_t(nvox) * C * 2);   // layer inputs / outputs (FP16)
+    xin.alloc(size_t(nvox) * 2);
+    pred.alloc(size_t(nvox) * 4);
+    dact[0].alloc(size_t(nvox) * C * 2);
+    dact[1].alloc(size_t(nvox) * C * 2);
+    nchunk = int(std::min<int64_t>(64, std::max<int64_t>(1, nvox / 64)));
+    part.alloc(size_t(nchunk) * (int64_t(C) * 27 * C + C) * 4);
+    dpart.alloc(4096 * 8);
+    scalar.alloc(8 * 8);
+    step_t = 0;
+    zero_moments();
+}
+
+void Net::zero_moments() {
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_fill_f32, dim3(gfor(n_params)), dim3(TPB), 0, s, n_params, m32.as<float>(), 0.f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(gfor(n_params)), dim3(TPB), 0, s, n_params, v32.as<float>(), 0.f);
+    step_t = 0;
+}
+
+void Net::sync_half() {
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_f32_to_f16, dim3(gfor(n_params)), dim3(TPB), 0, s, n_params, w32.as<float>(),
+                       w16.as<_Float16>());
+    TBH_HIP(hipGetLastError());
+}
+
+void Net::forward(const float* x_dev, float* y_dev) {
+    hipStream_t s = ctx->stream;
+    const Geo geo{g[0], g[1], g[2], nvox};
+    hipLaunchKernelGGL(k_f32_to_f16, dim3(gfor(nvox)), dim3(TPB), 0, s, nvox, x_dev, xin.as<_Float16>());
+    const _Float16* W = w16.as<_Float16>();
+    conv_launch<1, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
+    conv_launch<32, 32, 0>(geo, kDil[1], act[0].as<_Float16>(), W + off_w[1], W + off_b[1], nullptr, act[1].p, s);
+    conv_launch<32, 32, 0>(geo, kDil[2], act[1].as<_Float16>(), W + off_w[2], W + off_b[2], nullptr, act[2].p, s);
+    conv_launch<32, 1, 1>(geo, kDil[3], act[2].as<_Float16>(), W + off_w[3], W + off_b[3], nullptr,
+                          y_dev ? static_cast<void*>(y_dev) : pred.p, s);
+    TBH_HIP(hipGetLastError());
+}
+
+double Net::accumulate_gradients(const float* x_dev, const float* t_dev) {
+    hipStream_t s = ctx->stream;
+    const Geo geo{g[0], g[1], g[2], nvox};
+    forward(x_dev, nullptr);
+    // loss gradient 2 (pred - t) (sum of squares), FP16, into dact[0] as [nvox][1]
+    const int64_t gm = gfor(nvox);
+    _Float16* d3 = dact[0].as<_Float16>();
+    hipLaunchKernelGGL(k_mse, dim3(gm), dim3(TPB), 0, s, nvox, pred.as<float>(), t_dev, d3, dpart.as<double>());
+    hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, s, dpart.as<double>(), int(gm), scalar.as<double>());
+    const _Float16* W = w16.as<_Float16>();
+    _Float16* Wt = wt16.as<_Float16>();
+    float* gr = grad.as<float>();
+    float* pt = part.as<float>();
+    // layer 3 (32 -> 1): weight grads, then backward-data into layer-2 activations' grads
+    wgrad_launch<32, 1>(geo, kDil[3], act[2].as<_Float16>(), d3, pt, nchunk, gr + off_w[3], s);
+    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 1, 32, W + off_w[3],
+                       Wt + off_w[3]);
+    _Float16* d2 = dact[1].as<_Float16>();
+    conv_launch<1, 32, 2>(geo, kDil[3], d3, Wt + off_w[3], nullptr, act[2].as<_Float16>(), d2, s);
+    // layer 2 (32 -> 32)
+    wgrad_launch<32, 32>(geo, kDil[2], act[1].as<_Float16>(), d2, pt, nchunk, gr + off_w[2], s);
+    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 32, 32,
+                       W + off_w[2], Wt + off_w[2]);
+    _Float16* d1 = dact[0].as<_Float16>();
+    conv_launch<32, 32, 2>(geo, kDil[2], d2, Wt + off_w[2], nullptr, act[1].as<_Float16>(), d1, s);
+    // layer 1 (32 -> 32)
+    wgrad_launch<32, 32>(geo, kDil[1], act[0].as<_Float16>(), d1, pt, nchunk, gr + off_w[1], s);
+    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 32, 32,
+                       W + off_w[1], Wt + off_w[1]);
+    conv_launch<32, 32, 2>(geo, kDil[1], d1, Wt + off_w[1], nullptr, act[0].as<_Float16>(), d2, s);
+    // layer 0 (1 -> 32): weight grads only
+    wgrad_launch<1, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
+    TBH_HIP(hipGetLastError());
+    double loss = 0.0;
+    TBH_HIP(hipMemcpyAsync(&loss, scalar.p, 8, hipMemcpyDeviceToHost, s));
+    TBH_HIP(hipStreamSynchronize(s));
+    return loss / double(nvox);
+}
+
+void Net::zero_grad() {
+    hipLaunchKernelGGL(k_fill_f32, dim3(gfor(n_params)), dim3(TPB), 0, ctx->stream, n_params, grad.as<float>(), 0.f);
+}
+
+void Net::adam(double lr, int batch) {
+    ++step_t;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - std::pow(b1, float(step_t)), c2 = 1.f - std::pow(b2, float(step_t));
+    // gradient of the mean over voxels and samples
+    const float gscale = float(1.0 / (double(nvox) * batch));
+    hipLaunchKernelGGL(k_adam, dim3(gfor(n_params)), dim3(TPB), 0, ctx->stream, n_params, w32.as<float>(),
+                       m32.as<float>(), v32.as<float>(), grad.as<float>(), w16.as<_Float16>(), gscale, float(lr),
+                       b1, b2, eps, c1, c2);
+    TBH_HIP(hipGetLastError());
+}
+
+}  // namespace tbh

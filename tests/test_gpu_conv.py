@@ -1,0 +1,102 @@
+"""GPU parity of the surrogate's kernels against the oracle network.
+
+The GPU keeps activations and weights in FP16 with FP32 accumulation; the
+oracle computes in FP64 on the same FP16-rounded weights, rounding each
+hidden layer's output to FP16 like the GPU stores it.  Bars: forward and
+gradients 1e-3 normwise per layer (a few FP16 rounding boundaries fall
+differently under FP32 vs FP64 accumulation, and the GPU stores upstream
+gradients in FP16); Adam's first step is -lr * sign(g) wherever the oracle
+gradient is not tiny.
+"""
+import numpy as np
+import pytest
+
+import paper_1003_4570_amd as tbh
+from oracle import conv as Cv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return tbh.Context(0)
+
+
+def _setup(grid, seed):
+    rng = np.random.default_rng(seed)
+    params = Cv.init_params(rng, channels=32)
+    for W, b in params:
+        b += (rng.standard_normal(b.shape) * 0.05).astype(np.float32)
+    nx, ny, nz = grid
+    x = np.zeros((nz, ny, nx), np.float32)
+    idx = rng.choice(x.size, size=max(3, x.size // 60), replace=False)
+    x.ravel()[idx] = 1.0
+    t = rng.standard_normal((nz, ny, nx)).astype(np.float32) * 0.5
+    return params, x, t
+
+
+def _halfp(params):
+    return [(W.astype(np.float16).astype(np.float64), b.astype(np.float16).astype(np.float64)) for W, b in params]
+
+
+@pytest.mark.parametrize("grid", [(12, 12, 32), (7, 5, 9), (32, 32, 24)])
+def test_forward_parity(ctx, grid):
+    import torch
+    params, x, _ = _setup(grid, 1)
+    net = tbh.Net(ctx, grid)
+    net.set_params(tbh.flatten_params(params))
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+    yr, _ = Cv.forward(x[None].astype(np.float64), _halfp(params), half_acts=True)
+    err = np.linalg.norm(y - yr[0]) / np.linalg.norm(yr[0])
+    print(grid, "forward rel err", err, flush=True)
+    assert err < 1e-3
+    # parameters round-trip in canonical order
+    assert np.array_equal(net.get_params(), tbh.flatten_params(params))
+
+
+def test_gradient_parity(ctx):
+    import torch
+    grid = (12, 12, 32)
+    params, x, t = _setup(grid, 2)
+    net = tbh.Net(ctx, grid)
+    net.set_params(tbh.flatten_params(params))
+    g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    hp = _halfp(params)
+    out, cache = Cv.forward(x[None].astype(np.float64), hp, half_acts=True)
+    lo, dout = Cv.mse(out, t[None].astype(np.float64))
+    gr = Cv.backward(hp, cache, dout)
+    assert loss == pytest.approx(lo, rel=1e-3)
+    G = tbh.unflatten_params(g)
+    for li in range(4):
+        for k in range(2):
+            ref = gr[li][k]
+            err = np.linalg.norm(G[li][k] - ref) / max(np.linalg.norm(ref), 1e-30)
+            print("layer", li, "W" if k == 0 else "b", "grad rel err", err, flush=True)
+            assert err < 1e-3
+
+
+def test_adam_first_step_and_loss_decreases(ctx):
+    import torch
+    grid = (12, 12, 32)
+    params, x, t = _setup(grid, 3)
+    net = tbh.Net(ctx, grid)
+    w0 = tbh.flatten_params(params)
+    net.set_params(w0)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    lr = 1e-3
+    l0 = net.train_step([xd], [td], lr=lr)
+    w1 = net.get_params()
+    hp = _halfp(params)
+    out, cache = Cv.forward(x[None].astype(np.float64), hp, half_acts=True)
+    _, dout = Cv.mse(out, t[None].astype(np.float64))
+    gref = tbh.flatten_params([(dW, db) for dW, db in Cv.backward(hp, cache, dout)]).astype(np.float64)
+    big = np.abs(gref) > 1e-2 * np.abs(gref).max()
+    want = w0.astype(np.float64) - lr * np.sign(gref)
+    assert np.abs(w1[big] - want[big]).max() < 1e-6 + 1e-6 * np.abs(want[big]).max()
+    losses = [l0]
+    for _ in range(30):
+        losses.append(net.train_step([xd], [td], lr=lr))
+    print("losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.8 * losses[0]
