@@ -20,7 +20,14 @@ struct LzDev {
 struct LzWork {
     DevBuf V, w, scal, part, coef;
     int m = 0;
+    int64_t dim = 0;
     bool reorth = false;
+    // captured recurrence, replayed while the key (buffers, m, reorth) holds
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void*> key;
+    void drop_graph();
     ~LzWork();
     void ensure(const Ham& h, int m, bool reorth);
     LzDev dev(int m) const;

@@ -484,10 +484,11 @@ int64_t grid_for(int64_t n) {
 // host driver
 // ---------------------------------------------------------------------------
 
-LzWork::~LzWork() = default;
 
 void LzWork::ensure(const Ham& h, int m, bool reorth) {
-    if (this->m == m && this->reorth == reorth && V.p) return;
+    if (this->m == m && this->reorth == reorth && V.p && dim == h.dim) return;
+    drop_graph();
+    dim = h.dim;
     const int64_t ns = h.dim * (h.cplx_h ? 2 : 1);
     const size_t esz = h.prec == TBH_F64 ? 8 : 4;
     TBH_REQUIRE(!reorth || m <= 4000, "full reorthogonalisation supports at most 4000 steps");
@@ -515,17 +516,24 @@ LzDev LzWork::dev(int m_) const {
     return d;
 }
 
-void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_dev,
-                        double* alpha_h, double* beta_h, int* steps_h, int* breakdown_h, double* hx_ms) {
-    hipStream_t st = h.ctx->stream;
+namespace {
+
+__global__ void k_zero(int64_t n, double* a) {
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) a[i] = 0.0;
+}
+
+// Every launch of an m-step recurrence, enqueued on st.  With ev non-null
+// the H.x launches are bracketed by events (direct launches only).
+void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_dev, hipStream_t st,
+                        std::vector<hipEvent_t>* ev) {
     const bool f64 = h.prec == TBH_F64;
     const bool cx = h.cplx_h;
     const int cs = cx ? 2 : 1;
     const int64_t n_el = h.dim, ns = n_el * cs;
     const size_t esz = f64 ? 8 : 4;
-    W.ensure(h, m, reorth);
     LzDev d = W.dev(m);
-    TBH_HIP(hipMemsetAsync(W.scal.p, 0, W.scal.bytes, st));
+    const int64_t nscal = int64_t(W.scal.bytes / sizeof(double));
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(nscal)), dim3(TPB), 0, st, nscal, W.scal.as<double>());
     double* part = W.part.as<double>();
     // v_0 = v0 / |v0|
     char* Vb = W.V.as<char>();
@@ -542,18 +550,12 @@ void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
     }
     const int64_t nblk_hx = hx_num_blocks(h.lay);
     const int64_t gv = grid_for(ns);
-    std::vector<hipEvent_t> ev;
-    if (hx_ms) {
-        *hx_ms = 0.0;
-        ev.resize(2 * size_t(m));
-        for (auto& e : ev) TBH_HIP(hipEventCreate(&e));
-    }
     // three rotating vectors without reorthogonalisation
     int iprev = 2, icur = 0, inext = 1;
     for (int j = 0; j < m; ++j) {
         void* vj = reorth ? vec(j) : vec(icur);
         void* vp = j == 0 ? nullptr : (reorth ? vec(j - 1) : vec(iprev));
-        void* vn = reorth ? vec(j + 1 < m + 1 ? j + 1 : j) : vec(inext);
+        void* vn = reorth ? vec(j + 1) : vec(inext);
         HxArgs a;
         a.blocks = h.blocks.p;
         a.nbr = h.nbr_d.as<int32_t>();
@@ -564,9 +566,9 @@ void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         a.xprev = vp;
         a.beta = d.beta + j;
         a.partial = part;
-        if (hx_ms) TBH_HIP(hipEventRecord(ev[2 * j], st));
+        if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j], st));
         hx_launch(h.lay, f64, a, st);
-        if (hx_ms) TBH_HIP(hipEventRecord(ev[2 * j + 1], st));
+        if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j + 1], st));
         hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(TPB), 0, st, part, nblk_hx, d, j, int(reorth));
         if (!reorth) {
             if (f64) {
@@ -588,17 +590,73 @@ void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
             inext = t;
         } else {
             orth_cgs2(h, W, d, j, st);
-            const int64_t gu = grid_for(n_el);
             if (f64)
                 hipLaunchKernelGGL(k_scale_next<double>, dim3(gv), dim3(TPB), 0, st, ns,
                                    W.w.as<double>(), static_cast<double*>(vn), d, 0);
             else
                 hipLaunchKernelGGL(k_scale_next<float>, dim3(gv), dim3(TPB), 0, st, ns,
                                    W.w.as<float>(), static_cast<float*>(vn), d, 0);
-            (void)gu;
         }
     }
     TBH_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void LzWork::drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+}
+
+LzWork::~LzWork() {
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_dev,
+                        double* alpha_h, double* beta_h, int* steps_h, int* breakdown_h, double* hx_ms) {
+    hipStream_t st = h.ctx->stream;
+    W.ensure(h, m, reorth);
+    if (hx_ms) {
+        // timed: direct launches with events around every H.x
+        std::vector<hipEvent_t> ev(2 * size_t(m));
+        for (auto& e : ev) TBH_HIP(hipEventCreate(&e));
+        enqueue_recurrence(h, W, m, reorth, v0_dev, st, &ev);
+        TBH_HIP(hipStreamSynchronize(st));
+        *hx_ms = 0.0;
+        for (int j = 0; j < m; ++j) {
+            float ms = 0.f;
+            TBH_HIP(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+            *hx_ms += ms;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    } else {
+        // the launch sequence depends only on these pointers and sizes: capture
+        // it once into a graph and replay it on later calls
+        const std::vector<const void*> key = {h.blocks.p, h.nbr_d.p, h.has_pot ? h.pot_d.p : nullptr, v0_dev,
+                                              W.V.p, W.w.p, W.scal.p, W.part.p, W.coef.p,
+                                              reinterpret_cast<const void*>(intptr_t(m)),
+                                              reinterpret_cast<const void*>(intptr_t(reorth))};
+        if (!W.exec || key != W.key) {
+            W.drop_graph();
+            if (!W.cap) TBH_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
+            TBH_HIP(hipStreamBeginCapture(W.cap, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_recurrence(h, W, m, reorth, v0_dev, W.cap, nullptr);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(W.cap, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            TBH_HIP(hipStreamEndCapture(W.cap, &W.graph));
+            TBH_HIP(hipGraphInstantiate(&W.exec, W.graph, nullptr, nullptr, 0));
+            W.key = key;
+        }
+        TBH_HIP(hipGraphLaunch(W.exec, st));
+    }
     std::vector<double> s(W.scal.bytes / sizeof(double));
     TBH_HIP(hipMemcpyAsync(s.data(), W.scal.p, W.scal.bytes, hipMemcpyDeviceToHost, st));
     TBH_HIP(hipStreamSynchronize(st));
@@ -609,14 +667,6 @@ void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         for (int j = 0; j < m; ++j) alpha_h[j] = j < steps ? s[j] : 0.0;
     if (beta_h)
         for (int j = 0; j < m; ++j) beta_h[j] = j < steps ? s[m + j + 1] : 0.0;
-    if (hx_ms) {
-        for (int j = 0; j < m; ++j) {
-            float ms = 0.f;
-            TBH_HIP(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
-            *hx_ms += ms;
-        }
-        for (auto& e : ev) (void)hipEventDestroy(e);
-    }
 }
 
 void orth_cgs2(Ham& h, LzWork& W, const LzDev& d, int j, hipStream_t st) {

@@ -159,3 +159,25 @@ def test_lanczos_deterministic(ctx):
     a1, b1, _ = tbh.lanczos_run(h, 80, p.v0, reorth=True)
     a2, b2, _ = tbh.lanczos_run(h, 80, p.v0, reorth=True)
     assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+def test_graph_replay_equals_direct_launches(ctx):
+    """The recurrence is captured once into a HIP graph and replayed; the
+    event-timed path launches directly.  Replays with eager work and
+    synchronisation in between must equal the direct launches bit for bit."""
+    import torch
+    p = W.problem_periodic_cube(2, seed=6, model=W.MODEL_SP3D5S, spin=1, kfrac=(0.1, 0.2, 0.0))
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f32", keep_f64=True))
+    a0, b0, _ = tbh.lanczos_run(h, 50, p.v0, reorth=True, time_hx=True)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for r in range(3):
+        a, b, _ = tbh.lanczos_run(h, 50, p.v0, reorth=True)
+        assert np.array_equal(a, a0) and np.array_equal(b, b0)
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+    a0, b0, _ = tbh.lanczos_run(h, 80, p.v0, reorth=False, time_hx=True)
+    for r in range(3):
+        a, b, _ = tbh.lanczos_run(h, 80, p.v0, reorth=False)
+        assert np.array_equal(a, a0) and np.array_equal(b, b0)
+        junk.mul_(0.5)
+        torch.cuda.synchronize()

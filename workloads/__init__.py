@@ -313,3 +313,31 @@ CONFIGS = {
     "c4": c4_batch,
     "c5": c5_slab,
 }
+
+
+# ---------------------------------------------------------------------------
+# Schrodinger-Poisson study slab and surrogate initialisation
+# ---------------------------------------------------------------------------
+
+STUDY_SLAB = dict(nx=3, ny=3, nz=8, n_donors=9)
+
+
+def study_slab(seed: int) -> Problem:
+    """Delta-doped slab used for the start-potential study: 3x3x8 cells
+    (576 atoms), 9 donors on the mid (001) plane (half a monolayer, the same
+    areal density as the 8x8x60-cell slab with 64 donors), same parameters
+    and geometry for every seed; only the donor layout and start vector
+    change with the seed."""
+    return c5_slab(seed, **STUDY_SLAB)
+
+
+def init_surrogate_weights(seed: int, channels: int = 32) -> np.ndarray:
+    """He-normal initial weights of the four 3x3x3 layers (1->C->C->C->1),
+    zero biases, flattened in canonical order W[co][ci][dz][dy][dx], b[co]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for co, ci in ((channels, 1), (channels, channels), (channels, channels), (1, channels)):
+        std = np.sqrt(2.0 / (27 * ci))
+        out.append((rng.standard_normal(co * ci * 27) * std).astype(np.float32))
+        out.append(np.zeros(co, np.float32))
+    return np.concatenate(out)
