@@ -109,6 +109,115 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 3}))
 
 
+def bench_c2(a):
+    """FP32 H.x / FP32 vectors with FP64 scalars against the all-FP64
+    pipeline on the 20^3-cell hard-wall spin-orbit cube (64,000 atoms,
+    complex H of dimension 1.28M): 16 eigenvalues nearest mid-gap, m steps
+    of Lanczos with full reorthogonalisation."""
+    import torch
+    import paper_1003_4570_amd as tbh
+    import workloads as W
+    m = a.c2_m
+    prob = W.c2_hardwall_so(0, m=m)
+    ctx = tbh.Context(0)
+    out = {"metric": "eigenvalue error FP32 pipeline vs FP64 (eV)", "unit": "eV", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": f"lanczos{m}_reorth_si20x20x20_hardwall_sp3d5s_so", "atoms": prob.n_atoms,
+                      "k": prob.k, "sigma_eV": prob.sigma}}
+    res = {}
+    for prec in ("f64", "f32"):
+        print(f"bench c2: build {prec}", file=sys.stderr, flush=True)
+        ham = tbh.build_hamiltonian(ctx, **tbh.problem_args(prob, prec=prec, keep_f64=(prec == "f32")))
+        v0 = torch.tensor(np.ascontiguousarray(prob.v0).view(np.float64), device="cuda")
+        x = torch.randn(ham.dim, dtype=ham.torch_dtype(), device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            tbh.apply_h(ham, x, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            tbh.apply_h(ham, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        hx_ms = e0.elapsed_time(e1) / 20
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = tbh.lanczos_eigs(ham, prob.sigma, prob.k, m, v0, reorth=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = dict(r=r, seconds=dt, hx_ms=hx_ms, hx_GBs=ham.info["hx_bytes"] / hx_ms / 1e6,
+                         n_found=r["report"]["n_found"])
+        print(f"bench c2: {prec} found {r['report']['n_found']} in {dt:.2f} s", file=sys.stderr, flush=True)
+        del ham
+    r64, r32 = res["f64"]["r"], res["f32"]["r"]
+    errs_raw, errs_ref = [], []
+    for e_raw, e_ref in zip(r32["evals"], r32["refined"]):
+        if len(r64["refined"]):
+            j = int(np.argmin(np.abs(r64["refined"] - e_ref)))
+            errs_raw.append(abs(e_raw - r64["refined"][j]))
+            errs_ref.append(abs(e_ref - r64["refined"][j]))
+    out["value"] = float(max(errs_ref)) if errs_ref else None
+    out["extra"] = dict(
+        n_found_f32=res["f32"]["n_found"], n_found_f64=res["f64"]["n_found"],
+        max_err_raw=float(max(errs_raw)) if errs_raw else None,
+        max_err_refined=float(max(errs_ref)) if errs_ref else None,
+        max_residual_f32=float(max(r32["res"])) if len(r32["res"]) else None,
+        seconds_f32=res["f32"]["seconds"], seconds_f64=res["f64"]["seconds"],
+        hx_ms_f32=res["f32"]["hx_ms"], hx_GBs_f32=res["f32"]["hx_GBs"],
+        hx_ms_f64=res["f64"]["hx_ms"], hx_GBs_f64=res["f64"]["hx_GBs"],
+        evals_f32_refined=[float(v) for v in r32["refined"]],
+        evals_f64_refined=[float(v) for v in r64["refined"]])
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(a):
+    """Batched multi-vector H.X: 48 periodic cells (edges 2..12 cells) x 4
+    k-points, sp3s* with spin-orbit, 16 complex right-hand vectors, in one
+    persistent graph launch (autotuned) against one launch per cell."""
+    import torch
+    import paper_1003_4570_amd as tbh
+    import workloads as W
+    print("bench c4: building 192 Hamiltonians", file=sys.stderr, flush=True)
+    items = W.c4_batch(0)
+    ctx = tbh.Context(0)
+    hams, Xs, Ys = [], [], []
+    atoms = 0
+    for prob, x in items:
+        h = tbh.build_hamiltonian(ctx, **tbh.problem_args(prob, multi_vector=True))
+        hams.append(h)
+        Xs.append(torch.from_numpy(x.astype(np.complex64)).cuda())
+        Ys.append(torch.empty_like(Xs[-1]))
+        atoms += prob.n_atoms
+    b = tbh.Batch(ctx, hams, Xs, Ys)
+    cfg = b.autotune(None)
+
+    def timeit(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_graph = timeit(b.apply)
+    t_sep = timeit(b.apply_separate)
+    per_atom = 5 * 10 * 10 * 8 + 16 + 2 * 10 * 16 * 8
+    byts = per_atom * atoms
+    flops = atoms * 2 * (5 * 10 * 10) * 16 * 4     # complex MACs: 4 real multiply-adds
+    out = {"metric": "batched multi-vector H.X GB/s", "value": round(byts / t_graph / 1e6, 1), "unit": "GB/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "c4_48cells_x4k_sp3s_so_16rhs", "atom_k_instances": atoms,
+                      "bytes_per_apply": byts},
+           "extra": dict(ms_graph=t_graph, ms_separate=t_sep, speedup_vs_separate=t_sep / t_graph,
+                         autotuned=cfg, tflops=flops / t_graph / 1e9,
+                         mfma_fp32_frac=flops / t_graph / 1e9 / 157.3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +226,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4"],
+                    help="c3: H.x GB/s in Lanczos (default); c2: FP32 vs FP64 eigenvalues; "
+                         "c4: batched multi-vector H.X")
+    ap.add_argument("--c2-m", type=int, default=500)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (single-GPU build)",
@@ -124,6 +237,12 @@ def main():
         sys.exit(2)
     if a.calibrate_copy:
         calibrate_copy()
+        return
+    if a.workload == "c2":
+        bench_c2(a)
+        return
+    if a.workload == "c4":
+        bench_c4(a)
         return
 
     import torch
