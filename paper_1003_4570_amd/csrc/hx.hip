@@ -127,6 +127,83 @@ __device__ __forceinline__ void stream_rows(const typename Vec16<T>::type* __res
     }
 }
 
+}  // namespace
+}  // namespace tbh
+
+#include <utility>
+namespace tbh { namespace {
+template <typename T, bool CPLX, int NO, int R, bool DIAG, int C>
+__device__ __forceinline__ void consume_chunk(const typename Vec16<T>::type& v, const T (&xv)[4][NO * (CPLX ? 2 : 1)],
+                                              const T (&xo)[R * (CPLX ? 2 : 1)], const T (&xa)[DIAG ? 1 : NO * (CPLX ? 2 : 1)],
+                                              T (&acc)[R * (CPLX ? 2 : 1)]) {
+    constexpr int CS = CPLX ? 2 : 1;
+    constexpr int K = 16 / sizeof(T);
+    constexpr int S = R * NO * CS;
+    constexpr int BC = (S + K - 1) / K;
+    if constexpr (C < 4 * BC || !DIAG) {
+        constexpr int seg = C / BC, cc = C % BC;
+#pragma unroll
+        for (int e = 0; e < K; e += CS) {
+            const int s = cc * K + e;
+            if (s < S) {
+                if constexpr (CPLX) {
+                    const int el = s / 2, r = el / NO, col = el % NO;
+                    const T br = v[e], bi = v[e + 1];
+                    T xr, xi;
+                    if constexpr (seg < 4) { xr = xv[seg][2 * col]; xi = xv[seg][2 * col + 1]; }
+                    else { xr = xa[2 * col]; xi = xa[2 * col + 1]; }
+                    acc[2 * r] = fma(br, xr, acc[2 * r]);
+                    acc[2 * r] = fma(-bi, xi, acc[2 * r]);
+                    acc[2 * r + 1] = fma(br, xi, acc[2 * r + 1]);
+                    acc[2 * r + 1] = fma(bi, xr, acc[2 * r + 1]);
+                } else {
+                    const int r = s / NO, col = s % NO;
+                    T xval;
+                    if constexpr (seg < 4) xval = xv[seg][col]; else xval = xa[col];
+                    acc[r] = fma(v[e], xval, acc[r]);
+                }
+            }
+        }
+    } else {
+        constexpr int cc = C - 4 * BC;
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            const int r = cc * K + e;
+            if (r < R) {
+#pragma unroll
+                for (int q = 0; q < CS; ++q) acc[r * CS + q] = fma(v[e], xo[r * CS + q], acc[r * CS + q]);
+            }
+        }
+    }
+}
+template <typename T, bool CPLX, int NO, int R, bool DIAG, int NCH, int D, int C>
+__device__ __forceinline__ void pipe_step(const typename Vec16<T>::type* __restrict__ src, int L,
+                                         typename Vec16<T>::type (&buf)[D], const T (&xv)[4][NO * (CPLX ? 2 : 1)],
+                                         const T (&xo)[R * (CPLX ? 2 : 1)],
+                                         const T (&xa)[DIAG ? 1 : NO * (CPLX ? 2 : 1)], T (&acc)[R * (CPLX ? 2 : 1)]) {
+    const typename Vec16<T>::type v = buf[C % D];
+    if constexpr (C + D < NCH) buf[C % D] = __builtin_nontemporal_load(src + (C + D) * L);
+    consume_chunk<T, CPLX, NO, R, DIAG, C>(v, xv, xo, xa, acc);
+}
+template <typename T, bool CPLX, int NO, int R, bool DIAG, int NCH, int D, int... Cs>
+__device__ __forceinline__ void pipe_all(std::integer_sequence<int, Cs...>, const typename Vec16<T>::type* __restrict__ src, int L,
+                                         typename Vec16<T>::type (&buf)[D], const T (&xv)[4][NO * (CPLX ? 2 : 1)],
+                                         const T (&xo)[R * (CPLX ? 2 : 1)],
+                                         const T (&xa)[DIAG ? 1 : NO * (CPLX ? 2 : 1)], T (&acc)[R * (CPLX ? 2 : 1)]) {
+    (pipe_step<T, CPLX, NO, R, DIAG, NCH, D, Cs>(src, L, buf, xv, xo, xa, acc), ...);
+}
+}}
+namespace tbh {
+namespace {
+// block chunks in flight per lane in the ring-buffered stream, and the
+// largest lane stream (in 16-byte chunks) that uses it
+#ifndef HX_RING
+#define HX_RING 8
+#endif
+#ifndef HX_PIPE_MAX
+#define HX_PIPE_MAX 128
+#endif
+
 struct HxK {
     const void* blocks;
     const int32_t* nbr;
@@ -166,39 +243,60 @@ __global__ __launch_bounds__(256) void hx_kernel(HxK a) {
 
     if (active) {
         const V* src = static_cast<const V*>(a.blocks) + (tile * (4 * BC + (DIAG ? (R + K - 1) / K : BC))) * L + lane;
-        int32_t nb[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) nb[b] = a.nbr[atom * 4 + b];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if (nb[b] >= 0) {
-                T xv[ROW];
-                load_row<T, ROW, ROWB>(x + int64_t(nb[b]) * ROW, xv);
-                stream_rows<T, CPLX, NO, R>(src + b * BC * L, L, xv, acc);
-            }
-        }
-        const V* osrc = src + 4 * BC * L;
+        constexpr int NCH = 4 * BC + (DIAG ? (R + K - 1) / K : BC);
         T xo[OWN];
         load_row<T, OWN, (R * CS * sizeof(T)) % 16 == 0 && ROWB % 16 == 0 ? 16 : ((R * CS * sizeof(T)) % 8 == 0 && ROWB % 8 == 0 ? 8 : 4)>(
             x + atom * ROW + g * OWN, xo);
-        if constexpr (DIAG) {
-            constexpr int OC = (R + K - 1) / K;
+        if constexpr (NCH <= HX_PIPE_MAX) {
+            // every gather first, then one ring-buffered stream of all block
+            // chunks (loads complete in issue order, so x must be in flight
+            // before the blocks for the stream's waits to stay shallow).  A
+            // dangling slot reads the atom's own x against its all-zero block.
+            T xv[4][ROW];
 #pragma unroll
-            for (int c = 0; c < OC; ++c) {
-                const V v = __builtin_nontemporal_load(osrc + c * L);
+            for (int b = 0; b < 4; ++b) {
+                const int32_t j = a.nbr[atom * 4 + b];
+                load_row<T, ROW, ROWB>(x + (j >= 0 ? int64_t(j) : atom) * ROW, xv[b]);
+            }
+            T xa[DIAG ? 1 : ROW];
+            if constexpr (!DIAG) load_row<T, ROW, ROWB>(x + atom * ROW, xa);
+            constexpr int D = NCH < HX_RING ? NCH : HX_RING;
+            V buf[D];
 #pragma unroll
-                for (int e = 0; e < K; ++e) {
-                    const int r = c * K + e;
-                    if (r < R) {
+            for (int c = 0; c < D; ++c) buf[c] = __builtin_nontemporal_load(src + c * L);
+            pipe_all<T, CPLX, NO, R, DIAG, NCH, D>(std::make_integer_sequence<int, NCH>{}, src, L, buf, xv, xo, xa, acc);
+        } else {
+            int32_t nb[4];
 #pragma unroll
-                        for (int q = 0; q < CS; ++q) acc[r * CS + q] = fma(v[e], xo[r * CS + q], acc[r * CS + q]);
-                    }
+            for (int b = 0; b < 4; ++b) nb[b] = a.nbr[atom * 4 + b];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (nb[b] >= 0) {
+                    T xv[ROW];
+                    load_row<T, ROW, ROWB>(x + int64_t(nb[b]) * ROW, xv);
+                    stream_rows<T, CPLX, NO, R>(src + b * BC * L, L, xv, acc);
                 }
             }
-        } else {
-            T xa[ROW];
-            load_row<T, ROW, ROWB>(x + atom * ROW, xa);
-            stream_rows<T, CPLX, NO, R>(osrc, L, xa, acc);
+            const V* osrc = src + 4 * BC * L;
+            if constexpr (DIAG) {
+                constexpr int OC = (R + K - 1) / K;
+#pragma unroll
+                for (int c = 0; c < OC; ++c) {
+                    const V v = __builtin_nontemporal_load(osrc + c * L);
+#pragma unroll
+                    for (int e = 0; e < K; ++e) {
+                        const int r = c * K + e;
+                        if (r < R) {
+#pragma unroll
+                            for (int q = 0; q < CS; ++q) acc[r * CS + q] = fma(v[e], xo[r * CS + q], acc[r * CS + q]);
+                        }
+                    }
+                }
+            } else {
+                T xa[ROW];
+                load_row<T, ROW, ROWB>(x + atom * ROW, xa);
+                stream_rows<T, CPLX, NO, R>(osrc, L, xa, acc);
+            }
         }
         if (a.pot) {
             const T u = T(a.pot[atom]);
