@@ -198,7 +198,7 @@ namespace {
 // block chunks in flight per lane in the ring-buffered stream, and the
 // largest lane stream (in 16-byte chunks) that uses it
 #ifndef HX_RING
-#define HX_RING 8
+#define HX_RING 12
 #endif
 #ifndef HX_PIPE_MAX
 #define HX_PIPE_MAX 128
@@ -321,21 +321,18 @@ __global__ __launch_bounds__(256) void hx_kernel(HxK a) {
             static_cast<T*>(a.y) + atom * ROW + g * OWN, acc);
     }
     if constexpr (LZ) {
-        // Re(x^H y) = sum over real scalars of x*y for interleaved complex
+        // Re(x^H y) = sum over real scalars of x*y for interleaved complex;
+        // one partial pair per wavefront (no workgroup barrier: a finished
+        // wavefront does not wait for its siblings)
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             pa += __shfl_xor(pa, off, 64);
             pw += __shfl_xor(pw, off, 64);
         }
-        __shared__ double red[4][2];
-        if (lane == 0) {
-            red[wave][0] = pa;
-            red[wave][1] = pw;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && a.partial) {
-            a.partial[2 * blockIdx.x] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
-            a.partial[2 * blockIdx.x + 1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+        if (lane == 0 && a.partial) {
+            const int64_t slot = int64_t(blockIdx.x) * 4 + wave;
+            a.partial[2 * slot] = pa;
+            a.partial[2 * slot + 1] = pw;
         }
     }
 }
@@ -400,7 +397,8 @@ bool hx_shape_supported(int n_o, bool cplx_h, int R) {
     return false;
 }
 
-int64_t hx_num_blocks(const Layout& lay) { return (lay.n_tiles + 3) / 4; }
+// partial-sum slots a fused Lanczos launch writes (one per wavefront)
+int64_t hx_num_blocks(const Layout& lay) { return 4 * ((lay.n_tiles + 3) / 4); }
 
 void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
     const bool c = lay.cs == 2;

@@ -121,6 +121,11 @@ def generate(out_dir, seeds, max_iter=400, budget_s=None):
 
 
 def load_dataset(data_dir):
+    """Converged layouts from a directory of per-layout files, or from one
+    packed .npz (arrays seeds, donor_map [n, nz, ny, nx], U [n, nz, ny, nx])."""
+    if os.path.isfile(data_dir):
+        d = np.load(data_dir)
+        return d["donor_map"].astype(np.float32), d["U"].astype(np.float64), [int(v) for v in d["seeds"]]
     xs, us, seeds = [], [], []
     for f in sorted(os.listdir(data_dir)):
         if not f.startswith("layout_") or not f.endswith(".npz"):

@@ -204,3 +204,17 @@ def test_hx_rows_match_csr():
     y = (H @ x).reshape(p.n_atoms, -1)
     atoms = [0, 5, 17, 63]
     assert np.abs(T.hx_rows(p, atoms, x) - y[atoms]).max() < 1e-12
+
+
+def test_gap_table_entries_reproduce():
+    """The stored gap-accepted seeds still give the stored bulk band edges
+    (coarse recomputation with the oracle's bulk H(k))."""
+    from oracle import gap_search as G
+    t = W.gap_table()
+    assert {"model1_spin0", "model1_spin1", "model0_spin0", "model0_spin1"} <= set(t)
+    for key, e in t.items():
+        par = W.draw_params(np.random.default_rng(e["seed"]), e["model"], e["spin"], 1)
+        v, c = G.band_edges(par, G.kpoints(e["grid"]))
+        assert c - v >= 0.5
+        assert abs(e["vbm"] - v) < 1e-12 and abs(e["cbm"] - c) < 1e-12
+        assert abs(e["mid"] - 0.5 * (e["vbm"] + e["cbm"])) < 1e-12
