@@ -298,6 +298,12 @@ def main():
                      "traffic": traffic, "kernel": "hx_kernel<float,real,10,10,diag,lanczos>",
                      "avg_launch_ms": round(hx_avg * 1e3, 4)},
     }
+    scf = os.path.join(ROOT, "profiles", "scf_learned_start.json")
+    if os.path.exists(scf):
+        # the second half of the metric: SCF time-to-converge, learned vs plain
+        # start, from the held-out evaluation run recorded with its command
+        with open(scf) as f:
+            out["scf_learned_vs_plain"] = json.load(f).get("summary")
     if not a.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_seconds)

@@ -379,16 +379,17 @@ int tbh_batch_configure(tbh_batch* b, int32_t grid, int32_t remap);
  * Learned start potential for the self-consistent loop: a 3-D
  * convolutional network maps the donor-count map to the potential.
  *
- * Four 3x3x3 convolutions 1 -> 32 -> 32 -> 32 -> 1, dilations (1, 2, 4, 1),
+ * Four 3x3x3 convolutions c_in -> 32 -> 32 -> 32 -> 1 (c_in = 1 or 4), dilations (1, 2, 4, 1),
  * ReLU after the first three, circular padding along x and y, zero padding
  * along z; FP16 activations and weights on the matrix cores with FP32
  * accumulation, FP32 master weights and Adam (beta 0.9 / 0.999, eps 1e-8).
  * Parameters (host, FP32) in canonical order: for each layer, W[c_out][c_in]
- * [dz][dy][dx] then b[c_out].  Maps are device FP32 [nz][ny][nx].
+ * [dz][dy][dx] then b[c_out].  Inputs are device FP32 [c_in][nz][ny][nx],
+ * outputs device FP32 [nz][ny][nx].
  * ------------------------------------------------------------------------ */
 typedef struct tbh_net tbh_net;
 
-int tbh_net_create(tbh_ctx* ctx, int32_t channels, const int32_t grid[3], tbh_net** out);
+int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, const int32_t grid[3], tbh_net** out);
 int tbh_net_destroy(tbh_net* n);
 int tbh_net_num_params(const tbh_net* n, int64_t* count);
 /* Copy parameters in (resets the Adam moments) or out (host FP32). */

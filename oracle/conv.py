@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 The paper's self-consistent loop starts from some potential and iterates
 (Sec. III-A); the surrogate proposes that start from the donor map.  The
 network is fixed here by its definition: four 3x3x3 convolutions
-1 -> C -> C -> C -> 1 with dilations (1, 2, 4, 1), ReLU after the first three,
+c_in -> C -> C -> C -> 1 with dilations (1, 2, 4, 1), ReLU after the first three,
 circular padding along x and y (the slab is periodic there) and zero padding
 along z.  Tensors are [channels, nz, ny, nx]; weights [c_out, c_in, 3, 3, 3]
 indexed [dz][dy][dx] with tap offset (d - 1) * dilation.
@@ -60,9 +60,9 @@ def conv3d_backward(x, W, dil, dy):
     return dx, dW, db
 
 
-def init_params(rng, channels=32, scale=None):
+def init_params(rng, channels=32, scale=None, in_channels=1):
     """He-style random init for the four layers (FP32-representable)."""
-    shapes = [(channels, 1), (channels, channels), (channels, channels), (1, channels)]
+    shapes = [(channels, in_channels), (channels, channels), (channels, channels), (1, channels)]
     params = []
     for co, ci in shapes:
         std = np.sqrt(2.0 / (27 * ci)) if scale is None else scale

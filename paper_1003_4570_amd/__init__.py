@@ -131,7 +131,8 @@ _SIGS = [
     ("tbh_batch_autotune", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]),
     ("tbh_batch_configure", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
-    ("tbh_net_create", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]),
+    ("tbh_net_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_void_p)]),
     ("tbh_net_destroy", C.c_int, [C.c_void_p]),
     ("tbh_net_num_params", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("tbh_net_set_params", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -607,13 +608,16 @@ class Batch:
 
 class Net:
     """The convolutional start-potential surrogate (device kernels).
-    grid = (nx, ny, nz); maps are float32 device tensors [nz, ny, nx]."""
+    grid = (nx, ny, nz); inputs are float32 device tensors [in_channels, nz,
+    ny, nx] (or [nz, ny, nx] for one channel), outputs [nz, ny, nx]."""
 
-    def __init__(self, ctx: Context, grid, channels=32):
+    def __init__(self, ctx: Context, grid, channels=32, in_channels=1):
         self.ctx = ctx
         self.grid = tuple(int(g) for g in grid)
+        self.in_channels = int(in_channels)
         h = C.c_void_p()
-        _check(lib().tbh_net_create(ctx.h, int(channels), (C.c_int32 * 3)(*self.grid), C.byref(h)))
+        _check(lib().tbh_net_create(ctx.h, int(channels), self.in_channels, (C.c_int32 * 3)(*self.grid),
+                                    C.byref(h)))
         self.h = h
         n = C.c_int64(0)
         _check(lib().tbh_net_num_params(self.h, C.byref(n)))
@@ -629,24 +633,25 @@ class Net:
         _check(lib().tbh_net_get_params(self.h, w.ctypes.data))
         return w
 
-    def _chk(self, t):
+    def _chk(self, t, channels=1):
         import torch
         nx, ny, nz = self.grid
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
-                and t.is_contiguous() and t.numel() == nx * ny * nz):
-            raise TypeError("maps must be contiguous float32 device tensors [nz, ny, nx]")
+                and t.is_contiguous() and t.numel() == channels * nx * ny * nz):
+            raise TypeError(f"maps must be contiguous float32 device tensors [{channels}, nz, ny, nx]")
 
     def forward(self, x, y=None):
         import torch
-        self._chk(x)
+        self._chk(x, self.in_channels)
         if y is None:
-            y = torch.empty_like(x)
+            nx, ny, nz = self.grid
+            y = torch.empty((nz, ny, nx), dtype=torch.float32, device=x.device)
         self._chk(y)
         _check(lib().tbh_net_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
         return y
 
     def gradients(self, x, t):
-        self._chk(x)
+        self._chk(x, self.in_channels)
         self._chk(t)
         g = np.empty(self.n_params, np.float32)
         loss = C.c_double(0)
@@ -655,7 +660,9 @@ class Net:
         return g, loss.value
 
     def train_step(self, xs, ts, lr=1e-3):
-        for a in list(xs) + list(ts):
+        for a in xs:
+            self._chk(a, self.in_channels)
+        for a in ts:
             self._chk(a)
         n = len(xs)
         X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
@@ -681,8 +688,8 @@ def flatten_params(params):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
 
 
-def unflatten_params(flat, channels=32):
-    shapes = [(channels, 1), (channels, channels), (channels, channels), (1, channels)]
+def unflatten_params(flat, channels=32, in_channels=1):
+    shapes = [(channels, in_channels), (channels, channels), (channels, channels), (1, channels)]
     out, o = [], 0
     for co, ci in shapes:
         nW = co * ci * 27

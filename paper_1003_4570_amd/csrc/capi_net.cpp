@@ -42,12 +42,12 @@ void to_canonical(const tbh::Net& n, const float* in, float* out) {
 
 extern "C" {
 
-int tbh_net_create(tbh_ctx* ctx, int32_t channels, const int32_t grid[3], tbh_net** out) {
+int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, const int32_t grid[3], tbh_net** out) {
     return guard([&] {
         TBH_REQUIRE(ctx && grid && out, "null argument");
         TBH_HIP(hipSetDevice(ctx->device));
         const int g[3] = {grid[0], grid[1], grid[2]};
-        auto n = std::make_unique<tbh_net>(ctx, channels, g);
+        auto n = std::make_unique<tbh_net>(ctx, channels, in_channels, g);
         std::vector<float> z(n->n_params, 0.f);
         TBH_HIP(hipMemcpy(n->w32.p, z.data(), z.size() * 4, hipMemcpyHostToDevice));
         n->sync_half();

@@ -2,8 +2,9 @@
 // and training kernels.
 //
 // The self-consistent loop of the paper (Sec. III-A) iterates from a start
-// potential; this network maps the donor-count map to a start potential.
-// Four 3x3x3 convolutions 1 -> C -> C -> C -> 1 with dilations (1, 2, 4, 1),
+// potential; this network maps input maps derived from the donor layout to a
+// start potential.  Four 3x3x3 convolutions c_in -> C -> C -> C -> 1 with
+// dilations (1, 2, 4, 1),
 // ReLU after the first three, circular padding along x and y, zero padding
 // along z.  Activations are FP16, channels-last [voxel][channel]; weights are
 // FP32 masters with FP16 copies, laid out [c_out][tap][c_in] with
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(TPB) void k_conv(Geo g, int dil, const _Float16* __
         h4 a;
         if constexpr (CIN % 4 == 0) {
             const int tap = k0 / CIN, ci = k0 % CIN;
-            const int64_t s = vin ? shifted_voxel(g, v, tap, dil) : -1;
+            const int64_t s = (vin && k0 < K) ? shifted_voxel(g, v, tap, dil) : -1;
             if (s >= 0) a = *reinterpret_cast<const h4*>(in + s * CIN + ci);
             else a = h4{0, 0, 0, 0};
         } else {
@@ -185,6 +186,12 @@ __global__ void k_sum_part(const double* part, int n, double* out) {
     }
 }
 
+// [cin][nvox] FP32 -> [nvox][cin] FP16
+__global__ void k_pack_input(int64_t nvox, int cin, const float* a, _Float16* b) {
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < nvox; i += int64_t(gridDim.x) * TPB)
+        for (int c = 0; c < cin; ++c) b[i * cin + c] = _Float16(a[int64_t(c) * nvox + i]);
+}
+
 __global__ void k_f32_to_f16(int64_t n, const float* a, _Float16* b) {
     for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
         b[i] = _Float16(a[i]);
@@ -248,14 +255,15 @@ void wgrad_launch(const Geo& g, int dil, const _Float16* in, const _Float16* dou
 
 static const int kDil[4] = {1, 2, 4, 1};
 
-Net::Net(Ctx* c, int channels, const int grid[3]) : ctx(c), C(channels) {
+Net::Net(Ctx* c, int channels, int in_channels, const int grid[3]) : ctx(c), C(channels), CI(in_channels) {
     TBH_REQUIRE(channels == 32, "the surrogate kernels are built for 32 channels");
+    TBH_REQUIRE(in_channels == 1 || in_channels == 4, "the surrogate kernels take 1 or 4 input channels");
     for (int a = 0; a < 3; ++a) {
         TBH_REQUIRE(grid[a] > 0, "grid sizes must be positive");
         g[a] = grid[a];
     }
     nvox = int64_t(g[0]) * g[1] * g[2];
-    const int cin[4] = {1, C, C, C}, cout[4] = {C, C, C, 1};
+    const int cin[4] = {CI, C, C, C}, cout[4] = {C, C, C, 1};
     n_params = 0;
     for (int l = 0; l < 4; ++l) {
         off_w[l] = n_params;
@@ -272,7 +280,7 @@ Net::Net(Ctx* c, int channels, const int grid[3]) : ctx(c), C(channels) {
     w16.alloc(n_params * 2);
     wt16.alloc(n_params * 2);
     for (int l = 0; l < 4; ++l) act[l].alloc(size_t(nvox) * C * 2);   // layer inputs / outputs (FP16)
-    xin.alloc(size_t(nvox) * 2);
+    xin.alloc(size_t(nvox) * CI * 2);
     pred.alloc(size_t(nvox) * 4);
     dact[0].alloc(size_t(nvox) * C * 2);
     dact[1].alloc(size_t(nvox) * C * 2);
@@ -301,9 +309,12 @@ void Net::sync_half() {
 void Net::forward(const float* x_dev, float* y_dev) {
     hipStream_t s = ctx->stream;
     const Geo geo{g[0], g[1], g[2], nvox};
-    hipLaunchKernelGGL(k_f32_to_f16, dim3(gfor(nvox)), dim3(TPB), 0, s, nvox, x_dev, xin.as<_Float16>());
+    hipLaunchKernelGGL(k_pack_input, dim3(gfor(nvox)), dim3(TPB), 0, s, nvox, CI, x_dev, xin.as<_Float16>());
     const _Float16* W = w16.as<_Float16>();
-    conv_launch<1, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
+    if (CI == 4)
+        conv_launch<4, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
+    else
+        conv_launch<1, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
     conv_launch<32, 32, 0>(geo, kDil[1], act[0].as<_Float16>(), W + off_w[1], W + off_b[1], nullptr, act[1].p, s);
     conv_launch<32, 32, 0>(geo, kDil[2], act[1].as<_Float16>(), W + off_w[2], W + off_b[2], nullptr, act[2].p, s);
     conv_launch<32, 1, 1>(geo, kDil[3], act[2].as<_Float16>(), W + off_w[3], W + off_b[3], nullptr,
@@ -342,7 +353,10 @@ double Net::accumulate_gradients(const float* x_dev, const float* t_dev) {
                        W + off_w[1], Wt + off_w[1]);
     conv_launch<32, 32, 2>(geo, kDil[1], d1, Wt + off_w[1], nullptr, act[0].as<_Float16>(), d2, s);
     // layer 0 (1 -> 32): weight grads only
-    wgrad_launch<1, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
+    if (CI == 4)
+        wgrad_launch<4, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
+    else
+        wgrad_launch<1, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
     TBH_HIP(hipGetLastError());
     double loss = 0.0;
     TBH_HIP(hipMemcpyAsync(&loss, scalar.p, 8, hipMemcpyDeviceToHost, s));

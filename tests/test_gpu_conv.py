@@ -24,31 +24,35 @@ def ctx():
     return tbh.Context(0)
 
 
-def _setup(grid, seed):
+def _setup(grid, seed, cin=1):
     rng = np.random.default_rng(seed)
-    params = Cv.init_params(rng, channels=32)
+    params = Cv.init_params(rng, channels=32, in_channels=cin)
     for W, b in params:
         b += (rng.standard_normal(b.shape) * 0.05).astype(np.float32)
     nx, ny, nz = grid
-    x = np.zeros((nz, ny, nx), np.float32)
-    idx = rng.choice(x.size, size=max(3, x.size // 60), replace=False)
-    x.ravel()[idx] = 1.0
+    x = np.zeros((cin, nz, ny, nx), np.float32)
+    idx = rng.choice(nz * ny * nx, size=max(3, nz * ny * nx // 60), replace=False)
+    x[0].ravel()[idx] = 1.0
+    for c in range(1, cin):
+        x[c] = rng.standard_normal((nz, ny, nx)).astype(np.float32) * 0.3
     t = rng.standard_normal((nz, ny, nx)).astype(np.float32) * 0.5
-    return params, x, t
+    return params, (x if cin > 1 else x[0]), t
 
 
 def _halfp(params):
     return [(W.astype(np.float16).astype(np.float64), b.astype(np.float16).astype(np.float64)) for W, b in params]
 
 
-@pytest.mark.parametrize("grid", [(12, 12, 32), (7, 5, 9), (32, 32, 24)])
-def test_forward_parity(ctx, grid):
+@pytest.mark.parametrize("grid,cin", [((12, 12, 32), 1), ((7, 5, 9), 1), ((32, 32, 24), 1),
+                                      ((12, 12, 32), 4), ((7, 5, 9), 4)])
+def test_forward_parity(ctx, grid, cin):
     import torch
-    params, x, _ = _setup(grid, 1)
-    net = tbh.Net(ctx, grid)
+    params, x, _ = _setup(grid, 1, cin)
+    net = tbh.Net(ctx, grid, in_channels=cin)
     net.set_params(tbh.flatten_params(params))
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
-    yr, _ = Cv.forward(x[None].astype(np.float64), _halfp(params), half_acts=True)
+    xr = x.astype(np.float64) if cin > 1 else x[None].astype(np.float64)
+    yr, _ = Cv.forward(xr.astype(np.float16).astype(np.float64), _halfp(params), half_acts=True)
     err = np.linalg.norm(y - yr[0]) / np.linalg.norm(yr[0])
     print(grid, "forward rel err", err, flush=True)
     assert err < 1e-3
@@ -56,19 +60,21 @@ def test_forward_parity(ctx, grid):
     assert np.array_equal(net.get_params(), tbh.flatten_params(params))
 
 
-def test_gradient_parity(ctx):
+@pytest.mark.parametrize("cin", [1, 4])
+def test_gradient_parity(ctx, cin):
     import torch
     grid = (12, 12, 32)
-    params, x, t = _setup(grid, 2)
-    net = tbh.Net(ctx, grid)
+    params, x, t = _setup(grid, 2, cin)
+    net = tbh.Net(ctx, grid, in_channels=cin)
     net.set_params(tbh.flatten_params(params))
     g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     hp = _halfp(params)
-    out, cache = Cv.forward(x[None].astype(np.float64), hp, half_acts=True)
+    xr = (x.astype(np.float64) if cin > 1 else x[None].astype(np.float64)).astype(np.float16).astype(np.float64)
+    out, cache = Cv.forward(xr, hp, half_acts=True)
     lo, dout = Cv.mse(out, t[None].astype(np.float64))
     gr = Cv.backward(hp, cache, dout)
     assert loss == pytest.approx(lo, rel=1e-3)
-    G = tbh.unflatten_params(g)
+    G = tbh.unflatten_params(g, in_channels=cin)
     for li in range(4):
         for k in range(2):
             ref = gr[li][k]

@@ -115,3 +115,42 @@ def test_hardwall_dangling_and_reverse_slot():
         for b in range(4):
             ok = nbr[:, b] >= 0
             assert np.array_equal(nbr[nbr[ok, b], b], np.flatnonzero(ok))
+
+
+def test_study_slab_input_maps():
+    """Surrogate input maps of the study slab: the two sublattice masks are
+    disjoint, hold one atom each per occupied node (half the atoms each),
+    and an A node plus (1,1,1) is a B node; the donor map counts the donors."""
+    p = W.study_slab(3)
+    g = p.extra["grid"]
+    m = W.sublattice_masks(p.pos_q, g)
+    assert m.shape == (2, g[2], g[1], g[0])
+    assert m[0].sum() == m[1].sum() == p.pos_q.shape[0] // 2
+    assert (m[0] * m[1]).sum() == 0
+    za, ya, xa = np.nonzero(m[0])
+    inside = za + 1 < g[2]
+    assert np.all(m[1][za[inside] + 1, (ya[inside] + 1) % g[1], (xa[inside] + 1) % g[0]] == 1)
+    d = W.donor_map(p.pos_q, p.extra["donor_atoms"], g)
+    assert d.sum() == len(p.extra["donor_atoms"])
+    assert np.all((d > 0) <= (m[0] + m[1] > 0))
+
+
+def test_lattice_shifts_are_symmetries_of_the_study_slab():
+    """The in-plane translations used for the surrogate's symmetrized mean
+    and augmentation map the atom set and the donor-plane site set of the
+    study slab onto themselves; a symmetrized map is invariant under them."""
+    from paper_1003_4570_amd import surrogate as S
+    p = W.study_slab(0)
+    g = p.extra["grid"]
+    sh = S.lattice_shifts(g)
+    assert len(sh) == 18 and (0, 0) in sh
+    atoms = set(map(tuple, p.pos_q.tolist()))
+    for sx, sy in sh:
+        moved = {((x + sx) % g[0], (y + sy) % g[1], z) for x, y, z in atoms}
+        assert moved == atoms
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((g[2], g[1], g[0]))
+    s = S.symmetrize(a, g)
+    for sx, sy in sh:
+        assert np.allclose(np.roll(s, (sy, sx), axis=(-2, -1)), s)
+    assert np.isclose(s.mean(), a.mean())

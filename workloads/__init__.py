@@ -297,6 +297,17 @@ def draw_donor_sites(rng, pos_q: np.ndarray, plane_qz: int, n_donors: int) -> np
     return np.sort(sites[pick]).astype(np.int32)
 
 
+def sublattice_masks(pos_q: np.ndarray, grid: tuple) -> np.ndarray:
+    """[2][nz][ny][nx] float32: 1 on the grid nodes holding an A-sublattice
+    (first map) or B-sublattice (second map) atom."""
+    nx, ny, nz = grid
+    m = np.zeros((2, nz, ny, nx), dtype=np.float32)
+    q = np.asarray(pos_q)
+    sub = (q.sum(axis=1) % 4 == 3).astype(np.int64)
+    m[sub, q[:, 2], q[:, 1], q[:, 0]] = 1.0
+    return m
+
+
 def donor_map(pos_q: np.ndarray, donor_atoms: np.ndarray, grid: tuple) -> np.ndarray:
     """Donor-count map on the a/4 grid, shape [nz][ny][nx] (float32)."""
     nx, ny, nz = grid
@@ -331,12 +342,13 @@ def study_slab(seed: int) -> Problem:
     return c5_slab(seed, **STUDY_SLAB)
 
 
-def init_surrogate_weights(seed: int, channels: int = 32) -> np.ndarray:
-    """He-normal initial weights of the four 3x3x3 layers (1->C->C->C->1),
-    zero biases, flattened in canonical order W[co][ci][dz][dy][dx], b[co]."""
+def init_surrogate_weights(seed: int, channels: int = 32, in_channels: int = 1) -> np.ndarray:
+    """He-normal initial weights of the four 3x3x3 layers
+    (c_in->C->C->C->1), zero biases, flattened in canonical order
+    W[co][ci][dz][dy][dx], b[co]."""
     rng = np.random.default_rng(seed)
     out = []
-    for co, ci in ((channels, 1), (channels, channels), (channels, channels), (1, channels)):
+    for co, ci in ((channels, in_channels), (channels, channels), (channels, channels), (1, channels)):
         std = np.sqrt(2.0 / (27 * ci))
         out.append((rng.standard_normal(co * ci * 27) * std).astype(np.float32))
         out.append(np.zeros(co, np.float32))
