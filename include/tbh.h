@@ -213,7 +213,10 @@ typedef struct {
     double sigma;          /* target energy (eV) */
     int32_t k;             /* distinct eigenvalues wanted (>= 1) */
     int32_t max_iter;      /* Lanczos steps m (1..100000) */
-    int32_t reorth;        /* 0: none (three vectors); 1: full CGS2 (m+1 vectors) */
+    int32_t reorth;        /* 0: none; 1: full CGS2.  tbh_lanczos_run keeps three vectors
+                              without reorthogonalisation and m+1 with it; tbh_lanczos_eigs
+                              always keeps all m+1 (Ritz vectors need them), i.e.
+                              (m+1) * dim * element bytes of device memory. */
     int32_t n_cand;        /* Ritz pairs examined; 0 = min(m, max(4k, k+16)) */
     double res_tol;        /* converged iff |H y - theta y| <= res_tol, |y| = 1 (0 = 1e-4 eV) */
     double merge_tol;      /* converged values closer than this are one eigenvalue (0 = 1e-6 eV) */
@@ -238,7 +241,11 @@ typedef struct {
  * the FP64 copy of H (the ham must have one: TBH_F64, or TBH_F32 built with
  * keep_f64).  Converged candidates within merge_tol are one eigenvalue; the
  * k distinct converged values nearest sigma (ties: lower value) are returned
- * in ascending order.
+ * in ascending order.  Without reorthogonalisation the recurrence loses
+ * orthogonality once Ritz values converge and repeats them ("ghost" copies,
+ * Paige's analysis); each copy converges to the same eigenvalue and is merged
+ * by merge_tol, so long runs (thousands of steps, memory permitting) reach
+ * interior eigenvalues at the cost of H.x alone.
  * Outputs (host, [k], may be NULL): evals = raw Ritz values, refined =
  * Rayleigh quotients, res = residuals (eV), copies = converged copies merged
  * into the value.  evecs_dev (device, may be NULL): [k][dim] FP64 unit Ritz

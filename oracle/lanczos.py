@@ -64,9 +64,15 @@ def lanczos(hx, v0, m, reorth=True, breakdown_rel=1e-12):
 
 
 def tridiag_eig(alpha, beta):
-    """Eigenvalues ascending and eigenvectors of T (FP64, LAPACK stemr)."""
+    """Eigenvalues ascending and eigenvectors of T (FP64, LAPACK stemr; the
+    implicit-QL driver stev when stemr reports non-convergence, which it does
+    on the tight clusters that ghost copies of a long unreorthogonalised run
+    form)."""
     off = beta[: len(alpha) - 1]
-    return eigh_tridiagonal(alpha, off)
+    try:
+        return eigh_tridiagonal(alpha, off)
+    except np.linalg.LinAlgError:
+        return eigh_tridiagonal(alpha, off, lapack_driver="stev")
 
 
 def select_converged(theta, res, refined, sigma, k, merge_tol=1e-6, res_tol=1e-4):

@@ -116,7 +116,7 @@ int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, doubl
         tbh::LzWork& W = workspace(*h);
         int steps = 0, brk = 0;
         tbh::lanczos_recurrence(*h, W, o->max_iter, o->reorth != 0, v0, nullptr, nullptr, &steps, &brk,
-                                nullptr);
+                                nullptr, /*keep_basis=*/true);
         TBH_REQUIRE(steps >= 1, "Lanczos made no step");
         int ncand = o->n_cand > 0 ? o->n_cand : std::min(steps, std::max(4 * o->k, o->k + 16));
         ncand = std::min(ncand, steps);

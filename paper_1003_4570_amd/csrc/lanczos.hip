@@ -485,14 +485,15 @@ int64_t grid_for(int64_t n) {
 // ---------------------------------------------------------------------------
 
 
-void LzWork::ensure(const Ham& h, int m, bool reorth) {
-    if (this->m == m && this->reorth == reorth && V.p && dim == h.dim) return;
+void LzWork::ensure(const Ham& h, int m, bool reorth, bool keep_basis) {
+    const bool want_full = reorth || keep_basis;
+    if (this->m == m && this->reorth == reorth && full == want_full && V.p && dim == h.dim) return;
     drop_graph();
     dim = h.dim;
     const int64_t ns = h.dim * (h.cplx_h ? 2 : 1);
     const size_t esz = h.prec == TBH_F64 ? 8 : 4;
     TBH_REQUIRE(!reorth || m <= 4000, "full reorthogonalisation supports at most 4000 steps");
-    const int64_t nvec = reorth ? int64_t(m) + 1 : 3;
+    const int64_t nvec = want_full ? int64_t(m) + 1 : 3;
     V.alloc(size_t(nvec) * ns * esz);
     w.alloc(size_t(ns) * esz);
     scal.alloc(sizeof(double) * (2 * size_t(m) + 2 + LZ_NCTRL));
@@ -505,6 +506,7 @@ void LzWork::ensure(const Ham& h, int m, bool reorth) {
     coef.alloc(sizeof(double) * 2 * (size_t(m) + 1));
     this->m = m;
     this->reorth = reorth;
+    full = want_full;
 }
 
 LzDev LzWork::dev(int m_) const {
@@ -550,12 +552,13 @@ void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
     }
     const int64_t nblk_hx = hx_num_blocks(h.lay);
     const int64_t gv = grid_for(ns);
-    // three rotating vectors without reorthogonalisation
+    // the whole basis, or three rotating vectors
+    const bool full = W.full;
     int iprev = 2, icur = 0, inext = 1;
     for (int j = 0; j < m; ++j) {
-        void* vj = reorth ? vec(j) : vec(icur);
-        void* vp = j == 0 ? nullptr : (reorth ? vec(j - 1) : vec(iprev));
-        void* vn = reorth ? vec(j + 1) : vec(inext);
+        void* vj = full ? vec(j) : vec(icur);
+        void* vp = j == 0 ? nullptr : (full ? vec(j - 1) : vec(iprev));
+        void* vn = full ? vec(j + 1) : vec(inext);
         HxArgs a;
         a.blocks = h.blocks.p;
         a.nbr = h.nbr_d.as<int32_t>();
@@ -616,9 +619,10 @@ LzWork::~LzWork() {
 }
 
 void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_dev,
-                        double* alpha_h, double* beta_h, int* steps_h, int* breakdown_h, double* hx_ms) {
+                        double* alpha_h, double* beta_h, int* steps_h, int* breakdown_h, double* hx_ms,
+                        bool keep_basis) {
     hipStream_t st = h.ctx->stream;
-    W.ensure(h, m, reorth);
+    W.ensure(h, m, reorth, keep_basis);
     if (hx_ms) {
         // timed: direct launches with events around every H.x
         std::vector<hipEvent_t> ev(2 * size_t(m));
@@ -638,7 +642,8 @@ void lanczos_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         const std::vector<const void*> key = {h.blocks.p, h.nbr_d.p, h.has_pot ? h.pot_d.p : nullptr, v0_dev,
                                               W.V.p, W.w.p, W.scal.p, W.part.p, W.coef.p,
                                               reinterpret_cast<const void*>(intptr_t(m)),
-                                              reinterpret_cast<const void*>(intptr_t(reorth))};
+                                              reinterpret_cast<const void*>(intptr_t(reorth)),
+                                              reinterpret_cast<const void*>(intptr_t(W.full))};
         if (!W.exec || key != W.key) {
             W.drop_graph();
             if (!W.cap) TBH_HIP(hipStreamCreateWithFlags(&W.cap, hipStreamNonBlocking));
@@ -713,6 +718,7 @@ void tridiag_gpu(hipStream_t st, int m, const double* alpha_d, const double* bet
 }
 
 void ritz_pairs(Ham& h, LzWork& W, int steps, double sigma, int ncand, RitzOut& out) {
+    TBH_REQUIRE(W.full && steps <= W.m, "Ritz vectors need the whole Lanczos basis");
     hipStream_t st = h.ctx->stream;
     const bool f64 = h.prec == TBH_F64;
     const bool cx = h.cplx_h;

@@ -48,6 +48,7 @@ struct DevBuf {
         if (n == 0) return;
         if (hipMalloc(&p, n) != hipSuccess) {
             p = nullptr;
+            (void)hipGetLastError();   // clear the error so later status checks do not see it
             throw Error(TBH_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
         }
         bytes = n;

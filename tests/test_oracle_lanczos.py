@@ -62,6 +62,25 @@ def test_c1_nearest_distinct_match_dense(seed):
     assert (r["res"] <= 1e-4).all()
 
 
+def test_c1_without_reorth_ghosts_merge_to_dense_values():
+    """Without reorthogonalisation converged values reappear as ghost
+    copies; after merging, the 8 distinct values nearest sigma still equal
+    the dense spectrum's (each with more than one copy at 600 steps)."""
+    p = W.c1_lanczos_fp64(0)
+    H = T.hamiltonian(p)
+    r = L.lanczos_eigs(lambda x: H @ x, p.v0, 600, p.sigma, p.k, reorth=False)
+    ev = np.linalg.eigvalsh(H.toarray())
+    u = [ev[0]]
+    for e in ev[1:]:
+        if e - u[-1] > 1e-8:
+            u.append(e)
+    u = np.array(u)
+    want = np.sort(u[np.argsort(np.abs(u - p.sigma), kind="stable")[:p.k]])
+    assert len(r["theta"]) == p.k
+    assert np.abs(r["refined"] - want).max() < 1e-9
+    assert (np.asarray(r["copies"]) >= 2).any()
+
+
 def test_selection_rule():
     th = np.array([0.9, 1.0000001, 1.0000004, 1.3, 0.2, 5.0])
     res = np.array([1e-9, 1e-6, 1e-8, 1e-3, 1e-10, 1e-12])
