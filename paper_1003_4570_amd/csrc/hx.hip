@@ -16,8 +16,8 @@
 //  * workgroups are mapped XCD-contiguously, so the tiles one XCD processes
 //    are spatial neighbours and share their gathered x lines in that XCD's L2;
 //  * the Lanczos epilogue fuses y -= beta * x_prev and the FP64 partial sums
-//    of Re(x^H y) and |y|^2 (wavefront shuffles, then one LDS step per
-//    workgroup; no atomics, fixed order).
+//    of Re(x^H y) and |y|^2 (wavefront shuffles, one partial pair per
+//    wavefront; no atomics, fixed order).
 #include "tbh_internal.h"
 
 namespace tbh {
@@ -200,6 +200,9 @@ namespace {
 #ifndef HX_RING
 #define HX_RING 12
 #endif
+// wavefronts (tiles) per workgroup; 1, 2 and 4 measured the same on the
+// million-atom alloy (5.30-5.33 TB/s fused)
+constexpr int HX_WPB = 4;
 #ifndef HX_PIPE_MAX
 #define HX_PIPE_MAX 128
 #endif
@@ -218,7 +221,7 @@ struct HxK {
 };
 
 template <typename T, bool CPLX, int NO, int R, bool DIAG, bool LZ>
-__global__ __launch_bounds__(256) void hx_kernel(HxK a) {
+__global__ __launch_bounds__(64 * HX_WPB) void hx_kernel(HxK a) {
     constexpr int CS = CPLX ? 2 : 1;
     constexpr int G = NO / R, A = 64 / G, L = A * G;
     constexpr int K = 16 / sizeof(T);
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(256) void hx_kernel(HxK a) {
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t tile = blk * 4 + wave;
+    const int64_t tile = blk * HX_WPB + wave;
     const int64_t atom = tile * A + lane / G;
     const int g = lane % G;
     const bool active = tile < a.n_tiles && lane < L && atom < a.n_atoms;
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(256) void hx_kernel(HxK a) {
             pw += __shfl_xor(pw, off, 64);
         }
         if (lane == 0 && a.partial) {
-            const int64_t slot = int64_t(blockIdx.x) * 4 + wave;
+            const int64_t slot = int64_t(blockIdx.x) * HX_WPB + wave;
             a.partial[2 * slot] = pa;
             a.partial[2 * slot + 1] = pw;
         }
@@ -350,12 +353,12 @@ void launch_one(const Layout& lay, const HxArgs& h, hipStream_t s) {
     k.partial = h.partial;
     k.n_atoms = h.n_atoms;
     k.n_tiles = lay.n_tiles;
-    const int64_t nblk = (lay.n_tiles + 3) / 4;
+    const int64_t nblk = (lay.n_tiles + HX_WPB - 1) / HX_WPB;
     if (nblk == 0) return;
     if (h.partial)
-        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, true>), dim3(nblk), dim3(256), 0, s, k);
+        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, true>), dim3(nblk), dim3(64 * HX_WPB), 0, s, k);
     else
-        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, false>), dim3(nblk), dim3(256), 0, s, k);
+        hipLaunchKernelGGL((hx_kernel<T, CPLX, NO, R, DIAG, false>), dim3(nblk), dim3(64 * HX_WPB), 0, s, k);
 }
 
 template <typename T, bool CPLX, int NO, int R>
@@ -398,7 +401,7 @@ bool hx_shape_supported(int n_o, bool cplx_h, int R) {
 }
 
 // partial-sum slots a fused Lanczos launch writes (one per wavefront)
-int64_t hx_num_blocks(const Layout& lay) { return 4 * ((lay.n_tiles + 3) / 4); }
+int64_t hx_num_blocks(const Layout& lay) { return HX_WPB * ((lay.n_tiles + HX_WPB - 1) / HX_WPB); }
 
 void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
     const bool c = lay.cs == 2;

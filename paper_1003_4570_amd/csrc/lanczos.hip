@@ -63,25 +63,59 @@ __device__ double block_reduce_strided(const double* part, int64_t n, int stride
 // ---------------------------------------------------------------------------
 
 // After the fused hx kernel: alpha_j and (without reorthogonalisation) the
-// beta_{j+1} shortcut.
-__global__ void k_step_scalars(const double* part, int64_t nblk, LzDev d, int j, int reorth) {
+// beta_{j+1} shortcut.  The hx kernel leaves one (Re x^H y, |y|^2) pair per
+// wavefront (16k pairs for a million atoms); one 1024-thread block sums both
+// in a single pass of 16-byte loads with four independent accumulators per
+// thread, in a fixed order.
+constexpr int SCAL_TPB = 1024;
+
+__global__ __launch_bounds__(SCAL_TPB) void k_step_scalars(const double* part, int64_t nblk, LzDev d, int j,
+                                                           int reorth) {
     if (d.ctrl[LZ_BREAK] != 0.0) return;
-    const double a = block_reduce_strided(part, nblk, 2, 0);
-    const double ww = block_reduce_strided(part, nblk, 2, 1);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* p = reinterpret_cast<const d2*>(part);
+    d2 s0 = {0.0, 0.0}, s1 = {0.0, 0.0}, s2 = {0.0, 0.0}, s3 = {0.0, 0.0};
+    int64_t b = threadIdx.x;
+    for (; b + 3 * SCAL_TPB < nblk; b += 4 * SCAL_TPB) {
+        const d2 v0 = p[b], v1 = p[b + SCAL_TPB], v2 = p[b + 2 * SCAL_TPB], v3 = p[b + 3 * SCAL_TPB];
+        s0 += v0;
+        s1 += v1;
+        s2 += v2;
+        s3 += v3;
+    }
+    for (; b < nblk; b += SCAL_TPB) s0 += p[b];
+    const d2 t = (s0 + s1) + (s2 + s3);
+    double sa = t.x, sw = t.y;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sa += __shfl_xor(sa, off, 64);
+        sw += __shfl_xor(sw, off, 64);
+    }
+    __shared__ double sh[SCAL_TPB / 64][2];
+    if ((threadIdx.x & 63) == 0) {
+        sh[threadIdx.x >> 6][0] = sa;
+        sh[threadIdx.x >> 6][1] = sw;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double a = 0.0, ww = 0.0;
+    for (int w = 0; w < SCAL_TPB / 64; ++w) {
+        a += sh[w][0];
+        ww += sh[w][1];
+    }
     d.alpha[j] = a;
     d.ctrl[LZ_TMAX] = fmax(d.ctrl[LZ_TMAX], fabs(a));
     if (reorth) return;
     const double b2 = ww - a * a;
     if (b2 > 1e-8 * ww) {
-        const double b = sqrt(b2);
-        d.beta[j + 1] = b;
+        const double bb = sqrt(b2);
+        d.beta[j + 1] = bb;
         d.ctrl[LZ_FLAG] = 0.0;
-        d.ctrl[LZ_TMAX] = fmax(d.ctrl[LZ_TMAX], b);
-        if (b <= 1e-12 * d.ctrl[LZ_TMAX]) {
+        d.ctrl[LZ_TMAX] = fmax(d.ctrl[LZ_TMAX], bb);
+        if (bb <= 1e-12 * d.ctrl[LZ_TMAX]) {
             d.ctrl[LZ_BREAK] = 1.0;
         } else {
-            d.ctrl[LZ_INVB] = 1.0 / b;
+            d.ctrl[LZ_INVB] = 1.0 / bb;
         }
         d.ctrl[LZ_STEPS] = j + 1;
     } else {
@@ -572,7 +606,7 @@ void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j], st));
         hx_launch(h.lay, f64, a, st);
         if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j + 1], st));
-        hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(TPB), 0, st, part, nblk_hx, d, j, int(reorth));
+        hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, nblk_hx, d, j, int(reorth));
         if (!reorth) {
             if (f64) {
                 hipLaunchKernelGGL(k_lz_next<double>, dim3(gv), dim3(TPB), 0, st, ns, W.w.as<double>(),
