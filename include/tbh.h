@@ -383,20 +383,25 @@ int tbh_batch_autotune(tbh_batch* b, const char* cache_path, int32_t* grid, int3
 int tbh_batch_configure(tbh_batch* b, int32_t grid, int32_t remap);
 
 /* ------------------------------------------------------------------------
- * Learned start potential for the self-consistent loop: a 3-D
- * convolutional network maps the donor-count map to the potential.
+ * Learned start potential for the self-consistent loop (Sec. III-A starts
+ * it from a given potential): a 3-D convolutional network maps input maps
+ * of the donor layout to the potential.
  *
- * Four 3x3x3 convolutions c_in -> 32 -> 32 -> 32 -> 1 (c_in = 1 or 4), dilations (1, 2, 4, 1),
- * ReLU after the first three, circular padding along x and y, zero padding
- * along z; FP16 activations and weights on the matrix cores with FP32
- * accumulation, FP32 master weights and Adam (beta 0.9 / 0.999, eps 1e-8).
+ * n_layers 3x3x3 convolutions c_in -> 32 -> ... -> 32 -> 1 (c_in = 1 or 4,
+ * 2 <= n_layers <= 8) with one dilation per layer, ReLU after all but the
+ * last, circular padding along x and y, zero padding along z; FP16
+ * activations and weights on the matrix cores with FP32 accumulation, FP32
+ * master weights and Adam (beta 0.9 / 0.999, eps 1e-8).
  * Parameters (host, FP32) in canonical order: for each layer, W[c_out][c_in]
  * [dz][dy][dx] then b[c_out].  Inputs are device FP32 [c_in][nz][ny][nx],
  * outputs device FP32 [nz][ny][nx].
  * ------------------------------------------------------------------------ */
 typedef struct tbh_net tbh_net;
 
-int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, const int32_t grid[3], tbh_net** out);
+/* channels must be 32; dilations: host [n_layers] in 1..64, or NULL for the
+ * default 4-layer (1, 2, 4, 1); grid = (nx, ny, nz). */
+int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, int32_t n_layers,
+                   const int32_t* dilations, const int32_t grid[3], tbh_net** out);
 int tbh_net_destroy(tbh_net* n);
 int tbh_net_num_params(const tbh_net* n, int64_t* count);
 /* Copy parameters in (resets the Adam moments) or out (host FP32). */
@@ -404,7 +409,10 @@ int tbh_net_set_params(tbh_net* n, const float* params);
 int tbh_net_get_params(tbh_net* n, float* params);
 /* y = net(x). */
 int tbh_net_forward(tbh_net* n, const float* x_dev, float* y_dev);
-/* Gradient of the loss mean((net(x) - t)^2) w.r.t. the parameters (host,
+/* Per-voxel weights w of the training loss mean(w (net(x) - t)^2): device
+ * FP32 [nz][ny][nx], copied into the net; NULL restores w = 1. */
+int tbh_net_set_loss_weights(tbh_net* n, const float* w_dev);
+/* Gradient of the loss mean(w (net(x) - t)^2) w.r.t. the parameters (host,
  * canonical order) and the loss. */
 int tbh_net_gradients(tbh_net* n, const float* x_dev, const float* t_dev, float* grad, double* loss);
 /* One Adam step on the mean loss over a batch of (x[i], t[i]) device maps;

@@ -4,14 +4,15 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper's self-consistent loop starts from some potential and iterates
 (Sec. III-A); the surrogate proposes that start from the donor map.  The
-network is fixed here by its definition: four 3x3x3 convolutions
-c_in -> C -> C -> C -> 1 with dilations (1, 2, 4, 1), ReLU after the first three,
-circular padding along x and y (the slab is periodic there) and zero padding
-along z.  Tensors are [channels, nz, ny, nx]; weights [c_out, c_in, 3, 3, 3]
+network is fixed here by its definition: L 3x3x3 convolutions
+c_in -> C -> ... -> C -> 1, one dilation per layer (default four layers with
+dilations (1, 2, 4, 1)), ReLU after all but the last, circular padding along
+x and y (the slab is periodic there) and zero padding along z.  Tensors are [channels, nz, ny, nx]; weights [c_out, c_in, 3, 3, 3]
 indexed [dz][dy][dx] with tap offset (d - 1) * dilation.
 
-forward() optionally rounds every layer's output to FP16 (half_acts=True),
-the storage precision of the activations; arithmetic is FP64.
+forward() optionally rounds every layer's output to FP16 (half_acts=True)
+and backward() every upstream gradient (half_grads=True), the storage
+precision of activations and gradients on the device; arithmetic is FP64.
 """
 from __future__ import annotations
 
@@ -60,9 +61,9 @@ def conv3d_backward(x, W, dil, dy):
     return dx, dW, db
 
 
-def init_params(rng, channels=32, scale=None, in_channels=1):
-    """He-style random init for the four layers (FP32-representable)."""
-    shapes = [(channels, in_channels), (channels, channels), (channels, channels), (1, channels)]
+def init_params(rng, channels=32, scale=None, in_channels=1, n_layers=4):
+    """He-style random init of the layers (FP32-representable)."""
+    shapes = [(channels, in_channels)] + [(channels, channels)] * (n_layers - 2) + [(1, channels)]
     params = []
     for co, ci in shapes:
         std = np.sqrt(2.0 / (27 * ci)) if scale is None else scale
@@ -76,42 +77,51 @@ def _half(a):
     return a.astype(np.float16).astype(np.float64)
 
 
-def forward(x, params, half_acts=False, half_weights=False):
+def forward(x, params, half_acts=False, half_weights=False, dilations=DILATIONS):
     """Network output [1, nz, ny, nx] and the cache for backward."""
+    assert len(dilations) == len(params)
+    last = len(params) - 1
     acts = [x]
     pres = []
     h = x
-    for li, ((W, b), dil) in enumerate(zip(params, DILATIONS)):
+    for li, ((W, b), dil) in enumerate(zip(params, dilations)):
         Wl = _half(W) if half_weights else W
         bl = _half(b) if half_weights else b
         pre = conv3d(h, Wl, bl, dil)
         pres.append(pre)
-        h = np.maximum(pre, 0.0) if li < 3 else pre
-        if half_acts and li < 3:
+        h = np.maximum(pre, 0.0) if li < last else pre
+        if half_acts and li < last:
             h = _half(h)
         acts.append(h)
-    return h, dict(acts=acts, pres=pres)
+    return h, dict(acts=acts, pres=pres, dilations=tuple(dilations))
 
 
-def backward(params, cache, dout, half_weights=False):
-    """Gradients [(dW, db)] for dout = d loss / d output."""
-    grads = [None] * 4
-    g = dout
-    for li in range(3, -1, -1):
+def backward(params, cache, dout, half_weights=False, half_grads=False):
+    """Gradients [(dW, db)] for dout = d loss / d output.  half_grads rounds
+    the upstream gradient of every layer to FP16 (after the ReLU mask), the
+    precision the device stores it in; arithmetic stays FP64."""
+    dil = cache["dilations"]
+    last = len(params) - 1
+    grads = [None] * len(params)
+    g = _half(dout) if half_grads else dout
+    for li in range(last, -1, -1):
         W, b = params[li]
         Wl = _half(W) if half_weights else W
-        if li < 3:
+        if li < last:
             g = g * (cache["pres"][li] > 0)
-        dx, dW, db = conv3d_backward(cache["acts"][li], Wl, DILATIONS[li], g)
+            if half_grads:
+                g = _half(g)
+        dx, dW, db = conv3d_backward(cache["acts"][li], Wl, dil[li], g)
         grads[li] = (dW, db)
         g = dx
     return grads
 
 
-def mse(pred, target):
-    """mean((pred - target)^2) and its gradient."""
+def mse(pred, target, weight=None):
+    """mean(w (pred - target)^2) (w = 1 when weight is None) and its gradient."""
     d = pred - target
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    w = np.ones_like(d) if weight is None else np.broadcast_to(weight, d.shape)
+    return float(np.mean(w * d * d)), 2.0 * w * d / d.size
 
 
 def adam_step(w, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

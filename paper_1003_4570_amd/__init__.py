@@ -131,8 +131,9 @@ _SIGS = [
     ("tbh_batch_autotune", C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]),
     ("tbh_batch_configure", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
-    ("tbh_net_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
-                                 C.POINTER(C.c_void_p)]),
+    ("tbh_net_create", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_void_p)]),
+    ("tbh_net_set_loss_weights", C.c_int, [C.c_void_p, C.c_void_p]),
     ("tbh_net_destroy", C.c_int, [C.c_void_p]),
     ("tbh_net_num_params", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("tbh_net_set_params", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -611,13 +612,15 @@ class Net:
     grid = (nx, ny, nz); inputs are float32 device tensors [in_channels, nz,
     ny, nx] (or [nz, ny, nx] for one channel), outputs [nz, ny, nx]."""
 
-    def __init__(self, ctx: Context, grid, channels=32, in_channels=1):
+    def __init__(self, ctx: Context, grid, channels=32, in_channels=1, dilations=(1, 2, 4, 1)):
         self.ctx = ctx
         self.grid = tuple(int(g) for g in grid)
         self.in_channels = int(in_channels)
+        self.dilations = tuple(int(d) for d in dilations)
+        nl = len(self.dilations)
         h = C.c_void_p()
-        _check(lib().tbh_net_create(ctx.h, int(channels), self.in_channels, (C.c_int32 * 3)(*self.grid),
-                                    C.byref(h)))
+        _check(lib().tbh_net_create(ctx.h, int(channels), self.in_channels, nl, (C.c_int32 * nl)(*self.dilations),
+                                    (C.c_int32 * 3)(*self.grid), C.byref(h)))
         self.h = h
         n = C.c_int64(0)
         _check(lib().tbh_net_num_params(self.h, C.byref(n)))
@@ -639,6 +642,12 @@ class Net:
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
                 and t.is_contiguous() and t.numel() == channels * nx * ny * nz):
             raise TypeError(f"maps must be contiguous float32 device tensors [{channels}, nz, ny, nx]")
+
+    def set_loss_weights(self, w):
+        """Per-voxel training-loss weights (float32 device [nz, ny, nx]) or None."""
+        if w is not None:
+            self._chk(w)
+        _check(lib().tbh_net_set_loss_weights(self.h, None if w is None else C.c_void_p(w.data_ptr())))
 
     def forward(self, x, y=None):
         import torch
@@ -688,8 +697,8 @@ def flatten_params(params):
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params]).astype(np.float32)
 
 
-def unflatten_params(flat, channels=32, in_channels=1):
-    shapes = [(channels, in_channels), (channels, channels), (channels, channels), (1, channels)]
+def unflatten_params(flat, channels=32, in_channels=1, n_layers=4):
+    shapes = [(channels, in_channels)] + [(channels, channels)] * (n_layers - 2) + [(1, channels)]
     out, o = [], 0
     for co, ci in shapes:
         nW = co * ci * 27

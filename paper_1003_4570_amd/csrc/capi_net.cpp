@@ -15,7 +15,7 @@ namespace {
 // canonical W[co][ci][t] (t = dz*9 + dy*3 + dx) <-> internal W[co][t][ci]
 void to_internal(const tbh::Net& n, const float* in, std::vector<float>& out) {
     out.assign(n.n_params, 0.f);
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < n.L; ++l) {
         const int ci_n = n.lin[l], co_n = n.lout[l];
         for (int co = 0; co < co_n; ++co)
             for (int ci = 0; ci < ci_n; ++ci)
@@ -27,7 +27,7 @@ void to_internal(const tbh::Net& n, const float* in, std::vector<float>& out) {
 }
 
 void to_canonical(const tbh::Net& n, const float* in, float* out) {
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < n.L; ++l) {
         const int ci_n = n.lin[l], co_n = n.lout[l];
         for (int co = 0; co < co_n; ++co)
             for (int ci = 0; ci < ci_n; ++ci)
@@ -42,12 +42,18 @@ void to_canonical(const tbh::Net& n, const float* in, float* out) {
 
 extern "C" {
 
-int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, const int32_t grid[3], tbh_net** out) {
+int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, int32_t n_layers,
+                   const int32_t* dilations, const int32_t grid[3], tbh_net** out) {
     return guard([&] {
         TBH_REQUIRE(ctx && grid && out, "null argument");
+        TBH_REQUIRE(dilations || n_layers == 4, "dilations may be NULL only for 4 layers");
+        TBH_REQUIRE(n_layers >= 2 && n_layers <= tbh::Net::MAX_LAYERS, "n_layers must be in 2..8");
         TBH_HIP(hipSetDevice(ctx->device));
         const int g[3] = {grid[0], grid[1], grid[2]};
-        auto n = std::make_unique<tbh_net>(ctx, channels, in_channels, g);
+        int d[tbh::Net::MAX_LAYERS] = {1, 2, 4, 1};
+        if (dilations)
+            for (int l = 0; l < n_layers; ++l) d[l] = dilations[l];
+        auto n = std::make_unique<tbh_net>(ctx, channels, in_channels, n_layers, d, g);
         std::vector<float> z(n->n_params, 0.f);
         TBH_HIP(hipMemcpy(n->w32.p, z.data(), z.size() * 4, hipMemcpyHostToDevice));
         n->sync_half();
@@ -92,6 +98,15 @@ int tbh_net_get_params(tbh_net* n, float* params) {
         TBH_HIP(hipMemcpyAsync(w.data(), n->w32.p, w.size() * 4, hipMemcpyDeviceToHost, n->ctx->stream));
         TBH_HIP(hipStreamSynchronize(n->ctx->stream));
         to_canonical(*n, w.data(), params);
+    });
+}
+
+int tbh_net_set_loss_weights(tbh_net* n, const float* w_dev) {
+    return guard([&] {
+        TBH_REQUIRE(n, "null argument");
+        TBH_HIP(hipSetDevice(n->ctx->device));
+        n->set_loss_weights(w_dev);
+        TBH_HIP(hipStreamSynchronize(n->ctx->stream));
     });
 }
 

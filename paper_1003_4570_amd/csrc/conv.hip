@@ -3,9 +3,9 @@
 //
 // The self-consistent loop of the paper (Sec. III-A) iterates from a start
 // potential; this network maps input maps derived from the donor layout to a
-// start potential.  Four 3x3x3 convolutions c_in -> C -> C -> C -> 1 with
-// dilations (1, 2, 4, 1),
-// ReLU after the first three, circular padding along x and y, zero padding
+// start potential.  L 3x3x3 convolutions c_in -> C -> ... -> C -> 1 with a
+// dilation per layer (default four layers, dilations (1, 2, 4, 1)), ReLU
+// after all but the last, circular padding along x and y, zero padding
 // along z.  Activations are FP16, channels-last [voxel][channel]; weights are
 // FP32 masters with FP16 copies, laid out [c_out][tap][c_in] with
 // tap = dz*9 + dy*3 + dx (offset (d-1)*dilation).
@@ -163,13 +163,16 @@ __global__ void k_reduce_chunks(const float* part, int nchunk, int nw, float* gr
     grad[w] += float(s);
 }
 
-// pred FP32, target FP32: partial sum of squares, dout = 2 (pred - target) in FP16
-__global__ void k_mse(int64_t n, const float* pred, const float* target, _Float16* dout, double* part) {
+// pred FP32, target FP32, optional per-voxel weight w (null = 1): partial sum
+// of w (pred - target)^2, dout = 2 w (pred - target) in FP16
+__global__ void k_mse(int64_t n, const float* pred, const float* target, const float* w, _Float16* dout,
+                      double* part) {
     double acc = 0.0;
     for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
         const float d = pred[i] - target[i];
-        dout[i] = _Float16(2.f * d);
-        acc += double(d) * double(d);
+        const float wi = w ? w[i] : 1.f;
+        dout[i] = _Float16(2.f * wi * d);
+        acc += double(wi) * double(d) * double(d);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     __shared__ double sh[4];
@@ -253,25 +256,28 @@ void wgrad_launch(const Geo& g, int dil, const _Float16* in, const _Float16* dou
 // Net
 // ---------------------------------------------------------------------------
 
-static const int kDil[4] = {1, 2, 4, 1};
-
-Net::Net(Ctx* c, int channels, int in_channels, const int grid[3]) : ctx(c), C(channels), CI(in_channels) {
+Net::Net(Ctx* c, int channels, int in_channels, int n_layers, const int* dilations, const int grid[3])
+    : ctx(c), C(channels), CI(in_channels), L(n_layers) {
     TBH_REQUIRE(channels == 32, "the surrogate kernels are built for 32 channels");
     TBH_REQUIRE(in_channels == 1 || in_channels == 4, "the surrogate kernels take 1 or 4 input channels");
+    TBH_REQUIRE(n_layers >= 2 && n_layers <= MAX_LAYERS, "the surrogate takes 2 to 8 layers");
+    for (int l = 0; l < L; ++l) {
+        dil[l] = dilations ? dilations[l] : 1;
+        TBH_REQUIRE(dil[l] >= 1 && dil[l] <= 64, "dilations must be in 1..64");
+    }
     for (int a = 0; a < 3; ++a) {
         TBH_REQUIRE(grid[a] > 0, "grid sizes must be positive");
         g[a] = grid[a];
     }
     nvox = int64_t(g[0]) * g[1] * g[2];
-    const int cin[4] = {CI, C, C, C}, cout[4] = {C, C, C, 1};
     n_params = 0;
-    for (int l = 0; l < 4; ++l) {
+    for (int l = 0; l < L; ++l) {
+        lin[l] = l == 0 ? CI : C;
+        lout[l] = l == L - 1 ? 1 : C;
         off_w[l] = n_params;
-        n_params += int64_t(cout[l]) * 27 * cin[l];
+        n_params += int64_t(lout[l]) * 27 * lin[l];
         off_b[l] = n_params;
-        n_params += cout[l];
-        lin[l] = cin[l];
-        lout[l] = cout[l];
+        n_params += lout[l];
     }
     w32.alloc(n_params * 4);
     m32.alloc(n_params * 4);
@@ -279,7 +285,7 @@ Net::Net(Ctx* c, int channels, int in_channels, const int grid[3]) : ctx(c), C(c
     grad.alloc(n_params * 4);
     w16.alloc(n_params * 2);
     wt16.alloc(n_params * 2);
-    for (int l = 0; l < 4; ++l) act[l].alloc(size_t(nvox) * C * 2);   // layer inputs / outputs (FP16)
+    for (int l = 0; l + 1 < L; ++l) act[l].alloc(size_t(nvox) * C * 2);   // hidden activations (FP16)
     xin.alloc(size_t(nvox) * CI * 2);
     pred.alloc(size_t(nvox) * 4);
     dact[0].alloc(size_t(nvox) * C * 2);
@@ -290,6 +296,16 @@ Net::Net(Ctx* c, int channels, int in_channels, const int grid[3]) : ctx(c), C(c
     scalar.alloc(8 * 8);
     step_t = 0;
     zero_moments();
+}
+
+void Net::set_loss_weights(const float* w_dev) {
+    if (!w_dev) {
+        weighted = false;
+        return;
+    }
+    lw.alloc(size_t(nvox) * 4);
+    TBH_HIP(hipMemcpyAsync(lw.p, w_dev, size_t(nvox) * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    weighted = true;
 }
 
 void Net::zero_moments() {
@@ -312,12 +328,13 @@ void Net::forward(const float* x_dev, float* y_dev) {
     hipLaunchKernelGGL(k_pack_input, dim3(gfor(nvox)), dim3(TPB), 0, s, nvox, CI, x_dev, xin.as<_Float16>());
     const _Float16* W = w16.as<_Float16>();
     if (CI == 4)
-        conv_launch<4, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
+        conv_launch<4, 32, 0>(geo, dil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
     else
-        conv_launch<1, 32, 0>(geo, kDil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
-    conv_launch<32, 32, 0>(geo, kDil[1], act[0].as<_Float16>(), W + off_w[1], W + off_b[1], nullptr, act[1].p, s);
-    conv_launch<32, 32, 0>(geo, kDil[2], act[1].as<_Float16>(), W + off_w[2], W + off_b[2], nullptr, act[2].p, s);
-    conv_launch<32, 1, 1>(geo, kDil[3], act[2].as<_Float16>(), W + off_w[3], W + off_b[3], nullptr,
+        conv_launch<1, 32, 0>(geo, dil[0], xin.as<_Float16>(), W + off_w[0], W + off_b[0], nullptr, act[0].p, s);
+    for (int l = 1; l + 1 < L; ++l)
+        conv_launch<32, 32, 0>(geo, dil[l], act[l - 1].as<_Float16>(), W + off_w[l], W + off_b[l], nullptr,
+                               act[l].p, s);
+    conv_launch<32, 1, 1>(geo, dil[L - 1], act[L - 2].as<_Float16>(), W + off_w[L - 1], W + off_b[L - 1], nullptr,
                           y_dev ? static_cast<void*>(y_dev) : pred.p, s);
     TBH_HIP(hipGetLastError());
 }
@@ -326,37 +343,41 @@ double Net::accumulate_gradients(const float* x_dev, const float* t_dev) {
     hipStream_t s = ctx->stream;
     const Geo geo{g[0], g[1], g[2], nvox};
     forward(x_dev, nullptr);
-    // loss gradient 2 (pred - t) (sum of squares), FP16, into dact[0] as [nvox][1]
+    // loss gradient 2 w (pred - t) (weighted sum of squares), FP16, into dact[0] as [nvox][1]
     const int64_t gm = gfor(nvox);
-    _Float16* d3 = dact[0].as<_Float16>();
-    hipLaunchKernelGGL(k_mse, dim3(gm), dim3(TPB), 0, s, nvox, pred.as<float>(), t_dev, d3, dpart.as<double>());
+    hipLaunchKernelGGL(k_mse, dim3(gm), dim3(TPB), 0, s, nvox, pred.as<float>(), t_dev,
+                       weighted ? lw.as<float>() : static_cast<const float*>(nullptr), dact[0].as<_Float16>(),
+                       dpart.as<double>());
     hipLaunchKernelGGL(k_sum_part, dim3(1), dim3(64), 0, s, dpart.as<double>(), int(gm), scalar.as<double>());
     const _Float16* W = w16.as<_Float16>();
     _Float16* Wt = wt16.as<_Float16>();
     float* gr = grad.as<float>();
     float* pt = part.as<float>();
-    // layer 3 (32 -> 1): weight grads, then backward-data into layer-2 activations' grads
-    wgrad_launch<32, 1>(geo, kDil[3], act[2].as<_Float16>(), d3, pt, nchunk, gr + off_w[3], s);
-    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 1, 32, W + off_w[3],
-                       Wt + off_w[3]);
-    _Float16* d2 = dact[1].as<_Float16>();
-    conv_launch<1, 32, 2>(geo, kDil[3], d3, Wt + off_w[3], nullptr, act[2].as<_Float16>(), d2, s);
-    // layer 2 (32 -> 32)
-    wgrad_launch<32, 32>(geo, kDil[2], act[1].as<_Float16>(), d2, pt, nchunk, gr + off_w[2], s);
-    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 32, 32,
-                       W + off_w[2], Wt + off_w[2]);
-    _Float16* d1 = dact[0].as<_Float16>();
-    conv_launch<32, 32, 2>(geo, kDil[2], d2, Wt + off_w[2], nullptr, act[1].as<_Float16>(), d1, s);
-    // layer 1 (32 -> 32)
-    wgrad_launch<32, 32>(geo, kDil[1], act[0].as<_Float16>(), d1, pt, nchunk, gr + off_w[1], s);
-    hipLaunchKernelGGL(k_flip_weights, dim3((27 * 32 * 32 + TPB - 1) / TPB), dim3(TPB), 0, s, 32, 32,
-                       W + off_w[1], Wt + off_w[1]);
-    conv_launch<32, 32, 2>(geo, kDil[1], d1, Wt + off_w[1], nullptr, act[0].as<_Float16>(), d2, s);
-    // layer 0 (1 -> 32): weight grads only
+    // from the last layer down: weight gradients from the layer's input and
+    // upstream gradient, then backward-data through the layer into the
+    // gradient of its input activations (ReLU mask of that input applied)
+    int cur = 0;
+    for (int l = L - 1; l >= 1; --l) {
+        const _Float16* in = act[l - 1].as<_Float16>();
+        const _Float16* up = dact[cur].as<_Float16>();
+        _Float16* down = dact[1 - cur].as<_Float16>();
+        const int nw = lout[l] * 27 * lin[l];
+        hipLaunchKernelGGL(k_flip_weights, dim3((nw + TPB - 1) / TPB), dim3(TPB), 0, s, lout[l], lin[l],
+                           W + off_w[l], Wt + off_w[l]);
+        if (l == L - 1) {
+            wgrad_launch<32, 1>(geo, dil[l], in, up, pt, nchunk, gr + off_w[l], s);
+            conv_launch<1, 32, 2>(geo, dil[l], up, Wt + off_w[l], nullptr, in, down, s);
+        } else {
+            wgrad_launch<32, 32>(geo, dil[l], in, up, pt, nchunk, gr + off_w[l], s);
+            conv_launch<32, 32, 2>(geo, dil[l], up, Wt + off_w[l], nullptr, in, down, s);
+        }
+        cur = 1 - cur;
+    }
+    // layer 0: weight gradients only
     if (CI == 4)
-        wgrad_launch<4, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
+        wgrad_launch<4, 32>(geo, dil[0], xin.as<_Float16>(), dact[cur].as<_Float16>(), pt, nchunk, gr + off_w[0], s);
     else
-        wgrad_launch<1, 32>(geo, kDil[0], xin.as<_Float16>(), d2, pt, nchunk, gr + off_w[0], s);
+        wgrad_launch<1, 32>(geo, dil[0], xin.as<_Float16>(), dact[cur].as<_Float16>(), pt, nchunk, gr + off_w[0], s);
     TBH_HIP(hipGetLastError());
     double loss = 0.0;
     TBH_HIP(hipMemcpyAsync(&loss, scalar.p, 8, hipMemcpyDeviceToHost, s));

@@ -12,7 +12,8 @@ convolutional surrogate on them with the library's device kernels
 (tbh_net_*), and compares SCF time-to-converge from the zero start, the
 training-mean start and the learned start on held-out donor layouts.
 
-The network sees four maps on the a/4 grid: the donor count, the two
+The network (by default four layers; deeper dilation lists are supported)
+sees four maps on the a/4 grid: the donor count, the two
 sublattice occupation masks (a diamond lattice fills only one node in eight,
 and which nodes it fills is not invariant under a one-node shift, so without
 them a convolution cannot tell an atom site from an empty node) and the
@@ -99,7 +100,8 @@ class Study:
         """Load trained weights; returns start(dmap) -> device FP64 [nz, ny, nx]."""
         wz = np.load(weights)
         nz, ny, nx = wz["Tbar"].shape
-        net = tbh.Net(self.ctx, (nx, ny, nz), in_channels=N_IN)
+        dil = tuple(int(d) for d in wz["dilations"]) if "dilations" in wz.files else (1, 2, 4, 1)
+        net = tbh.Net(self.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dil)
         net.set_params(wz["params"])
         Tbar = self.torch.from_numpy(wz["Tbar"]).cuda()
         scale, fs, target = float(wz["scale"]), float(wz["feat_scale"]), str(wz["target"])
@@ -224,15 +226,27 @@ def symmetrize(a, grid):
     return np.mean([np.roll(a, (sy, sx), axis=(-2, -1)) for sx, sy in lattice_shifts(grid)], axis=0)
 
 
-def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", n_val=0, ctx=None):
+def near_plane_weights(grid, donor_z, near_weight, half_width=3):
+    """Loss weights 1 + near_weight on atom nodes within half_width grid
+    planes of the donor plane (where the start error is largest), 1
+    elsewhere; float32 [nz, ny, nx]."""
+    nx, ny, nz = grid
+    m = W.sublattice_masks(W.study_slab(0).pos_q, grid).sum(axis=0) > 0
+    z = np.arange(nz)[:, None, None]
+    return (1.0 + near_weight * (m & (np.abs(z - donor_z) <= half_width))).astype(np.float32)
+
+
+def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", n_val=0, ctx=None,
+          dilations=(1, 2, 4, 1), near_weight=0.0):
     """Fit the network to converged potentials.  target "U": the network
     gives U* directly; "E": it gives U* minus the bare-donor potential (the
     electron part), added back at inference.  The targets are taken relative
     to their training mean averaged over the lattice translations (an exact
     symmetry of the donor ensemble), and every epoch shows each layout under
-    a random lattice translation.  The last n_val layouts are held out and
-    the max-norm start error on them reported.  The learning rate follows a
-    cosine decay from lr to zero."""
+    a random lattice translation.  near_weight > 0 weights the loss on the
+    atoms next to the donor plane (near_plane_weights).  The last n_val
+    layouts are held out and the max-norm start error on them reported.  The
+    learning rate follows a cosine decay from lr to zero."""
     import torch
     st = Study(ctx)
     X, U, seeds = load_dataset(data_dir)
@@ -245,8 +259,11 @@ def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", 
     scale = float((Y[:ntr] - Tbar).std())
     T = ((Y - Tbar) / scale).astype(np.float32)
     nz, ny, nx = X.shape[1:]
-    net = tbh.Net(st.ctx, (nx, ny, nz), in_channels=N_IN)
-    net.set_params(W.init_surrogate_weights(seed, in_channels=N_IN))
+    net = tbh.Net(st.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dilations)
+    net.set_params(W.init_surrogate_weights(seed, in_channels=N_IN, n_layers=len(dilations)))
+    if near_weight > 0:
+        donor_z = int(np.flatnonzero(X.sum(axis=(0, 2, 3)))[0])
+        net.set_loss_weights(torch.from_numpy(near_plane_weights(grid, donor_z, near_weight)).cuda())
     Xd = [st.inputs(x, feat_scale) for x in X]
     Td = [torch.from_numpy(t).cuda() for t in T]
     shifts = lattice_shifts(grid)
@@ -285,7 +302,8 @@ def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", 
             print(json.dumps(rec), flush=True)
     torch.cuda.synchronize()
     np.savez(out_path, params=net.get_params(), Tbar=Tbar, scale=scale, feat_scale=feat_scale, target=target,
-             loss=np.array(hist), train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0)
+             dilations=np.array(dilations), near_weight=near_weight, loss=np.array(hist),
+             train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0)
     return hist
 
 
@@ -363,6 +381,9 @@ def main():
     t.add_argument("--target", choices=("U", "E"), default="U",
                    help="U: the converged potential; E: its electron part (minus the bare-donor potential)")
     t.add_argument("--val", type=int, default=0, help="hold out this many layouts and report their start error")
+    t.add_argument("--dilations", default="1,2,4,1", help="one dilation per layer")
+    t.add_argument("--near-weight", type=float, default=0.0,
+                   help="extra loss weight on the atoms next to the donor plane")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="1000:1016")
@@ -374,7 +395,8 @@ def main():
     elif a.cmd == "pack":
         print(json.dumps(dict(layouts=pack(a.out, a.sources))), flush=True)
     elif a.cmd == "train":
-        train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.target, a.val)
+        train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.target, a.val,
+              dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight)
     else:
         recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean)
         s = summarize(recs)

@@ -2,11 +2,13 @@
 
 The GPU keeps activations and weights in FP16 with FP32 accumulation; the
 oracle computes in FP64 on the same FP16-rounded weights, rounding each
-hidden layer's output to FP16 like the GPU stores it.  Bars: forward and
-gradients 1e-3 normwise per layer (a few FP16 rounding boundaries fall
-differently under FP32 vs FP64 accumulation, and the GPU stores upstream
-gradients in FP16); Adam's first step is -lr * sign(g) wherever the oracle
-gradient is not tiny.
+hidden layer's output and each upstream gradient to FP16 like the GPU
+stores them.  Bars: forward and gradients 1e-3 normwise per layer on random
+weights (a few FP16 rounding boundaries fall differently under FP32 vs FP64
+accumulation; through more layers those differences compound, so deeper
+nets and the weighted loss are checked instead on exactly representable
+weights and data, where the bar is 1e-6); Adam's first step is
+-lr * sign(g) wherever the oracle gradient is not tiny.
 """
 import numpy as np
 import pytest
@@ -24,9 +26,9 @@ def ctx():
     return tbh.Context(0)
 
 
-def _setup(grid, seed, cin=1):
+def _setup(grid, seed, cin=1, n_layers=4):
     rng = np.random.default_rng(seed)
-    params = Cv.init_params(rng, channels=32, in_channels=cin)
+    params = Cv.init_params(rng, channels=32, in_channels=cin, n_layers=n_layers)
     for W, b in params:
         b += (rng.standard_normal(b.shape) * 0.05).astype(np.float32)
     nx, ny, nz = grid
@@ -43,16 +45,18 @@ def _halfp(params):
     return [(W.astype(np.float16).astype(np.float64), b.astype(np.float16).astype(np.float64)) for W, b in params]
 
 
-@pytest.mark.parametrize("grid,cin", [((12, 12, 32), 1), ((7, 5, 9), 1), ((32, 32, 24), 1),
-                                      ((12, 12, 32), 4), ((7, 5, 9), 4)])
-def test_forward_parity(ctx, grid, cin):
+@pytest.mark.parametrize("grid,cin,dil", [((12, 12, 32), 1, (1, 2, 4, 1)), ((7, 5, 9), 1, (1, 2, 4, 1)),
+                                          ((32, 32, 24), 1, (1, 2, 4, 1)), ((12, 12, 32), 4, (1, 2, 4, 1)),
+                                          ((7, 5, 9), 4, (1, 2, 4, 1)), ((12, 12, 32), 4, (1, 2, 4, 8, 2, 1)),
+                                          ((7, 5, 9), 1, (2, 5))])
+def test_forward_parity(ctx, grid, cin, dil):
     import torch
-    params, x, _ = _setup(grid, 1, cin)
-    net = tbh.Net(ctx, grid, in_channels=cin)
+    params, x, _ = _setup(grid, 1, cin, len(dil))
+    net = tbh.Net(ctx, grid, in_channels=cin, dilations=dil)
     net.set_params(tbh.flatten_params(params))
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     xr = x.astype(np.float64) if cin > 1 else x[None].astype(np.float64)
-    yr, _ = Cv.forward(xr.astype(np.float16).astype(np.float64), _halfp(params), half_acts=True)
+    yr, _ = Cv.forward(xr.astype(np.float16).astype(np.float64), _halfp(params), half_acts=True, dilations=dil)
     err = np.linalg.norm(y - yr[0]) / np.linalg.norm(yr[0])
     print(grid, "forward rel err", err, flush=True)
     assert err < 1e-3
@@ -81,6 +85,64 @@ def test_gradient_parity(ctx, cin):
             err = np.linalg.norm(G[li][k] - ref) / max(np.linalg.norm(ref), 1e-30)
             print("layer", li, "W" if k == 0 else "b", "grad rel err", err, flush=True)
             assert err < 1e-3
+
+
+def _setup_exact(grid, seed, cin, nl):
+    """Sparse weights in {-1, 0, 1} (1 % non-zero), integer inputs, biases,
+    targets and loss weights: every activation and upstream gradient is a
+    small integer, exact in FP16 storage and FP32 accumulation, so device
+    and oracle must agree to the rounding of the final sums whatever the
+    depth."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for li in range(nl):
+        co = 1 if li == nl - 1 else 32
+        ci = cin if li == 0 else 32
+        W = rng.choice([-1.0, 1.0], size=(co, ci, 3, 3, 3)) * (rng.random((co, ci, 3, 3, 3)) < 0.01)
+        params.append((W, rng.integers(-1, 2, co).astype(np.float64)))
+    nx, ny, nz = grid
+    x = rng.integers(-2, 3, (cin, nz, ny, nx)).astype(np.float32)
+    t = rng.integers(-4, 5, (nz, ny, nx)).astype(np.float32)
+    w = rng.integers(1, 4, (nz, ny, nx)).astype(np.float32)
+    return params, x, t, w
+
+
+@pytest.mark.parametrize("cin,dil", [(4, (1, 2, 4, 8, 2, 1)), (1, (3, 1)), (4, (1, 2, 4, 1))])
+def test_gradient_exact_deep_and_weighted(ctx, cin, dil):
+    """Any depth and dilation list, weighted loss, on exactly representable
+    values: forward and every layer's gradients equal the oracle's to 1e-6."""
+    import torch
+    grid = (12, 12, 32)
+    nl = len(dil)
+    params, x, t, w = _setup_exact(grid, 7, cin, nl)
+    out, cache = Cv.forward(x.astype(np.float64), params, dilations=dil)
+    lo, dout = Cv.mse(out, t[None].astype(np.float64), w[None].astype(np.float64))
+    gr = Cv.backward(params, cache, dout)
+    # the premise: FP16 storage of activations and gradients changes nothing
+    out16, cache16 = Cv.forward(x.astype(np.float64), params, half_acts=True, dilations=dil)
+    gr16 = Cv.backward(params, cache16, dout * out.size, half_grads=True)
+    assert np.array_equal(out16, out)
+    assert all(np.abs(g16[0] / out.size - g[0]).max() <= 1e-12 * max(1.0, np.abs(g[0]).max())
+               for g16, g in zip(gr16, gr))
+    assert all((np.abs(g[0]) > 0).sum() > 100 for g in gr[:-1])
+    net = tbh.Net(ctx, grid, in_channels=cin, dilations=dil)
+    net.set_params(tbh.flatten_params(params))
+    net.set_loss_weights(torch.from_numpy(w).cuda())
+    xd = torch.from_numpy(x if cin > 1 else x[0]).contiguous().cuda()
+    y = net.forward(xd).cpu().numpy()
+    assert np.abs(y - out[0]).max() <= 1e-6 * max(1.0, np.abs(out).max())
+    g, loss = net.gradients(xd, torch.from_numpy(t).cuda())
+    assert loss == pytest.approx(lo, rel=1e-6)
+    G = tbh.unflatten_params(g, in_channels=cin, n_layers=nl)
+    for li in range(nl):
+        for k in range(2):
+            ref = gr[li][k]
+            err = np.linalg.norm(G[li][k] - ref) / max(np.linalg.norm(ref), 1e-30)
+            print("layer", li, "W" if k == 0 else "b", "grad rel err", err, flush=True)
+            assert err < 1e-6
+    net.set_loss_weights(None)
+    _, loss1 = net.gradients(xd, torch.from_numpy(t).cuda())
+    assert loss1 == pytest.approx(Cv.mse(out, t[None].astype(np.float64))[0], rel=1e-6)
 
 
 def test_adam_first_step_and_loss_decreases(ctx):

@@ -39,35 +39,52 @@ def test_conv_matches_brute_force(dil):
     assert np.abs(Cv.conv3d(x, W, b, dil) - _brute(x, W, b, dil)).max() < 1e-12
 
 
-def test_backward_finite_differences():
-    rng = np.random.default_rng(0)
-    params = Cv.init_params(rng, channels=4)
+@pytest.mark.parametrize("dil,cin,weighted", [((1, 2, 4, 1), 1, False), ((1, 2, 4, 8, 2, 1), 4, True),
+                                              ((2, 1), 1, True)])
+def test_backward_finite_differences(dil, cin, weighted):
+    rng = np.random.default_rng(len(dil))
+    params = Cv.init_params(rng, channels=4, in_channels=cin, n_layers=len(dil))
     for W, b in params:
         b += rng.standard_normal(b.shape) * 0.1
-    x = rng.standard_normal((1, 9, 6, 6))
+    x = rng.standard_normal((cin, 9, 6, 6))
     t = rng.standard_normal((1, 9, 6, 6))
-    out, cache = Cv.forward(x, params)
-    loss, dout = Cv.mse(out, t)
+    w = rng.uniform(0.5, 3.0, (1, 9, 6, 6)) if weighted else None
+
+    def loss_of():
+        return Cv.mse(Cv.forward(x, params, dilations=dil)[0], t, w)[0]
+
+    out, cache = Cv.forward(x, params, dilations=dil)
+    loss, dout = Cv.mse(out, t, w)
     grads = Cv.backward(params, cache, dout)
     eps = 1e-6
-    for li in range(4):
+    for li in range(len(dil)):
         W, b = params[li]
         for idx in [(0, 0, 1, 1, 1), (min(1, W.shape[0] - 1), W.shape[1] - 1, 0, 2, 1), (0, 0, 2, 0, 2)]:
             old = W[idx]
             W[idx] = old + eps
-            lp, _ = Cv.mse(Cv.forward(x, params)[0], t)
+            lp = loss_of()
             W[idx] = old - eps
-            lm, _ = Cv.mse(Cv.forward(x, params)[0], t)
+            lm = loss_of()
             W[idx] = old
             fd = (lp - lm) / (2 * eps)
             assert grads[li][0][idx] == pytest.approx(fd, rel=1e-6, abs=1e-10)
         old = b[0]
         b[0] = old + eps
-        lp, _ = Cv.mse(Cv.forward(x, params)[0], t)
+        lp = loss_of()
         b[0] = old - eps
-        lm, _ = Cv.mse(Cv.forward(x, params)[0], t)
+        lm = loss_of()
         b[0] = old
         assert grads[li][1][0] == pytest.approx((lp - lm) / (2 * eps), rel=1e-6, abs=1e-10)
+
+
+def test_weighted_mse_closed_forms():
+    rng = np.random.default_rng(5)
+    p, t = rng.standard_normal((1, 4, 3, 3)), rng.standard_normal((1, 4, 3, 3))
+    assert Cv.mse(p, t, np.ones_like(p))[0] == pytest.approx(Cv.mse(p, t)[0], rel=1e-15)
+    m = np.zeros_like(p)
+    m[0, 1] = 1.0
+    d = (p - t)[0, 1]
+    assert Cv.mse(p, t, m)[0] == pytest.approx(np.sum(d * d) / p.size, rel=1e-14)
 
 
 def test_translation_equivariance_xy():

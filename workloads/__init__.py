@@ -342,13 +342,13 @@ def study_slab(seed: int) -> Problem:
     return c5_slab(seed, **STUDY_SLAB)
 
 
-def init_surrogate_weights(seed: int, channels: int = 32, in_channels: int = 1) -> np.ndarray:
-    """He-normal initial weights of the four 3x3x3 layers
-    (c_in->C->C->C->1), zero biases, flattened in canonical order
-    W[co][ci][dz][dy][dx], b[co]."""
+def init_surrogate_weights(seed: int, channels: int = 32, in_channels: int = 1, n_layers: int = 4) -> np.ndarray:
+    """He-normal initial weights of the 3x3x3 layers (c_in->C->...->C->1),
+    zero biases, flattened in canonical order W[co][ci][dz][dy][dx], b[co]."""
     rng = np.random.default_rng(seed)
     out = []
-    for co, ci in ((channels, in_channels), (channels, channels), (channels, channels), (1, channels)):
+    shapes = [(channels, in_channels)] + [(channels, channels)] * (n_layers - 2) + [(1, channels)]
+    for co, ci in shapes:
         std = np.sqrt(2.0 / (27 * ci))
         out.append((rng.standard_normal(co * ci * 27) * std).astype(np.float32))
         out.append(np.zeros(co, np.float32))
