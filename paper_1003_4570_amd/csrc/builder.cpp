@@ -1,3 +1,5 @@
+#include <algorithm>
+#include <array>
 // Host model builder: input validation, neighbour table, Slater-Koster bond
 // blocks in closed form, on-site blocks, and packing into the layout the
 // H.x kernels stream.
@@ -328,14 +330,15 @@ Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool 
 namespace {
 
 template <typename T>
-void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t t0, int64_t t1) {
+void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t t0, int64_t t1,
+                const int64_t* perm) {
     const int no = M.n_o;
     std::vector<cplx> D(no * no), B(4 * no * no);
     for (int64_t t = t0; t < t1; ++t) {
         for (int la = 0; la < L.A; ++la) {
             const int64_t a = t * L.A + la;
             const bool live = a < M.n;
-            if (live) host_atom_blocks(M, a, D.data(), B.data());
+            if (live) host_atom_blocks(M, perm ? perm[a] : a, D.data(), B.data());
             for (int g = 0; g < L.G; ++g) {
                 const int lane = la * L.G + g;
                 auto put = [&](int s, double v) {
@@ -376,6 +379,25 @@ void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t 
 
 }  // namespace
 
+std::vector<int64_t> locality_order(const int32_t* q, int64_t n) {
+    // With this order the atoms of one basis class along a row of cells are
+    // consecutive, and so are their neighbours in any one bond direction
+    // (each is one fixed class of the other sublattice, one cell offset
+    // away): a wavefront's neighbour gathers then read runs of contiguous
+    // rows instead of 64 scattered ones.
+    auto key = [&](int64_t i) {
+        const int32_t* p = q + 3 * i;
+        const int cls = ((p[0] & 3) * 4 + (p[1] & 3)) * 4 + (p[2] & 3);
+        return std::array<int64_t, 4>{cls, p[2] >> 2, p[1] >> 2, p[0] >> 2};
+    };
+    std::vector<int64_t> perm(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i) perm[size_t(i)] = i;
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+    for (int64_t i = 0; i < n; ++i)
+        if (perm[size_t(i)] != i) return perm;
+    return {};
+}
+
 void pack_atom_major(const HostModel& M, int64_t stride, float* dst) {
     const int no = M.n_o;
     const int cs = M.cplx_h ? 2 : 1;
@@ -408,7 +430,7 @@ void pack_atom_major(const HostModel& M, int64_t stride, float* dst) {
     for (auto& t : th) t.join();
 }
 
-void pack_layout(const HostModel& M, const Layout& L, bool diag, void* dst) {
+void pack_layout(const HostModel& M, const Layout& L, bool diag, void* dst, const int64_t* perm) {
     unsigned nt = std::thread::hardware_concurrency();
     nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
     if (L.n_tiles < 64) nt = 1;
@@ -419,10 +441,10 @@ void pack_layout(const HostModel& M, const Layout& L, bool diag, void* dst) {
         if (t0 >= t1) break;
         if (L.esz == 8)
             th.emplace_back(pack_range<double>, std::cref(M), std::cref(L), diag,
-                            static_cast<double*>(dst), t0, t1);
+                            static_cast<double*>(dst), t0, t1, perm);
         else
             th.emplace_back(pack_range<float>, std::cref(M), std::cref(L), diag,
-                            static_cast<float*>(dst), t0, t1);
+                            static_cast<float*>(dst), t0, t1, perm);
     }
     for (auto& t : th) t.join();
 }

@@ -52,6 +52,36 @@ int choose_rows(int n_o, bool cplx_h, int prec, int64_t n_atoms, int lanes) {
 }  // namespace
 }  // namespace tbh
 
+namespace {
+
+// y = H x with x, y in the caller's atom order: straight through when the
+// stream order is the caller's, else through stream-order staging vectors
+void apply_in_caller_order(tbh::Ham& h, const void* blocks, const tbh::Layout& lay, bool f64, const void* x,
+                           void* y) {
+    tbh::HxArgs a;
+    a.blocks = blocks;
+    a.nbr = h.nbr_d.as<int32_t>();
+    a.pot = h.has_pot ? h.pot_d.as<double>() : nullptr;
+    a.n_atoms = h.n;
+    hipStream_t st = h.ctx->stream;
+    if (!h.permuted) {
+        a.x = x;
+        a.y = y;
+        tbh::hx_launch(lay, f64, a, st);
+        return;
+    }
+    const size_t row = size_t(h.n_o) * (h.cplx_h ? 2 : 1) * (f64 ? 8 : 4);
+    h.xs.alloc(row * size_t(h.n));
+    h.ys.alloc(row * size_t(h.n));
+    tbh::rows_to_stream(st, h.n, h.perm_d.as<int64_t>(), row, x, h.xs.p);
+    a.x = h.xs.p;
+    a.y = h.ys.p;
+    tbh::hx_launch(lay, f64, a, st);
+    tbh::rows_to_caller(st, h.n, h.perm_d.as<int64_t>(), row, h.ys.p, y);
+}
+
+}  // namespace
+
 extern "C" {
 
 int tbh_version(void) { return 100; }
@@ -137,20 +167,29 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         h->nbr_h = M.nbr;
         h->wrap_h = M.wrap;
         h->pos_h.assign(g->pos_q, g->pos_q + 3 * g->n_atoms);
+        // stream order (the multi-vector copy, built for many small cells,
+        // keeps the caller's order and so does every ham that has one)
+        if (!o->multi_vector) h->perm_h = tbh::locality_order(g->pos_q, M.n);
+        h->permuted = !h->perm_h.empty();
+        const int64_t* perm = h->permuted ? h->perm_h.data() : nullptr;
+        if (h->permuted) {
+            h->perm_d.alloc(h->perm_h.size() * 8);
+            TBH_HIP(hipMemcpy(h->perm_d.p, h->perm_h.data(), h->perm_h.size() * 8, hipMemcpyHostToDevice));
+        }
         // diagonal on-site blocks need no spin-orbit, no passivation
         h->diag = !M.spin && !(M.par.passivation_eV != 0.0 && M.n_dangling > 0);
         const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);
         h->lay = tbh::make_layout(M.n, M.n_o, M.cplx_h, o->prec, R, h->diag);
         {
             std::vector<char> host(size_t(h->lay.bytes));
-            tbh::pack_layout(M, h->lay, h->diag, host.data());
+            tbh::pack_layout(M, h->lay, h->diag, host.data(), perm);
             h->blocks.alloc(host.size());
             TBH_HIP(hipMemcpy(h->blocks.p, host.data(), host.size(), hipMemcpyHostToDevice));
         }
         if (o->prec == TBH_F32 && o->keep_f64) {
             h->lay64 = tbh::make_layout(M.n, M.n_o, M.cplx_h, TBH_F64, R, h->diag);
             std::vector<char> host(size_t(h->lay64.bytes));
-            tbh::pack_layout(M, h->lay64, h->diag, host.data());
+            tbh::pack_layout(M, h->lay64, h->diag, host.data(), perm);
             h->blocks64.alloc(host.size());
             TBH_HIP(hipMemcpy(h->blocks64.p, host.data(), host.size(), hipMemcpyHostToDevice));
             h->has_f64 = true;
@@ -167,7 +206,20 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
             h->has_mv = true;
         }
         h->nbr_d.alloc(M.nbr.size() * 4);
-        TBH_HIP(hipMemcpy(h->nbr_d.p, M.nbr.data(), M.nbr.size() * 4, hipMemcpyHostToDevice));
+        if (h->permuted) {
+            // neighbour table in stream order: slot k's neighbours, renumbered
+            std::vector<int64_t> inv(static_cast<size_t>(M.n));
+            for (int64_t k = 0; k < M.n; ++k) inv[size_t(perm[k])] = k;
+            std::vector<int32_t> nb(M.nbr.size());
+            for (int64_t k = 0; k < M.n; ++k)
+                for (int b = 0; b < 4; ++b) {
+                    const int32_t j = M.nbr[size_t(perm[k]) * 4 + b];
+                    nb[size_t(k) * 4 + b] = j >= 0 ? int32_t(inv[size_t(j)]) : -1;
+                }
+            TBH_HIP(hipMemcpy(h->nbr_d.p, nb.data(), nb.size() * 4, hipMemcpyHostToDevice));
+        } else {
+            TBH_HIP(hipMemcpy(h->nbr_d.p, M.nbr.data(), M.nbr.size() * 4, hipMemcpyHostToDevice));
+        }
         *out = h.release();
     });
 }
@@ -216,8 +268,11 @@ int tbh_ham_set_potential(tbh_ham* h, const double* pot_dev) {
             return;
         }
         h->pot_d.alloc(size_t(h->n) * 8);
-        TBH_HIP(hipMemcpyAsync(h->pot_d.p, pot_dev, size_t(h->n) * 8, hipMemcpyDeviceToDevice,
-                               h->ctx->stream));
+        if (h->permuted)
+            tbh::rows_to_stream(h->ctx->stream, h->n, h->perm_d.as<int64_t>(), 8, pot_dev, h->pot_d.p);
+        else
+            TBH_HIP(hipMemcpyAsync(h->pot_d.p, pot_dev, size_t(h->n) * 8, hipMemcpyDeviceToDevice,
+                                   h->ctx->stream));
         h->has_pot = true;
     });
 }
@@ -230,14 +285,7 @@ int tbh_apply_h(tbh_ham* h, const void* x, void* y, int32_t nrhs) {
         TBH_REQUIRE((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 16 == 0,
                     "x and y must be 16-byte aligned");
         TBH_HIP(hipSetDevice(h->ctx->device));
-        tbh::HxArgs a;
-        a.blocks = h->blocks.p;
-        a.nbr = h->nbr_d.as<int32_t>();
-        a.x = x;
-        a.y = y;
-        a.pot = h->has_pot ? h->pot_d.as<double>() : nullptr;
-        a.n_atoms = h->n;
-        tbh::hx_launch(h->lay, h->prec == TBH_F64, a, h->ctx->stream);
+        apply_in_caller_order(*h, h->blocks.p, h->lay, h->prec == TBH_F64, x, y);
     });
 }
 
@@ -249,15 +297,8 @@ int tbh_apply_h_f64(tbh_ham* h, const double* x, double* y) {
         TBH_REQUIRE((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 16 == 0,
                     "x and y must be 16-byte aligned");
         TBH_HIP(hipSetDevice(h->ctx->device));
-        tbh::HxArgs a;
         const bool main64 = h->prec == TBH_F64;
-        a.blocks = main64 ? h->blocks.p : h->blocks64.p;
-        a.nbr = h->nbr_d.as<int32_t>();
-        a.x = x;
-        a.y = y;
-        a.pot = h->has_pot ? h->pot_d.as<double>() : nullptr;
-        a.n_atoms = h->n;
-        tbh::hx_launch(main64 ? h->lay : h->lay64, true, a, h->ctx->stream);
+        apply_in_caller_order(*h, main64 ? h->blocks.p : h->blocks64.p, main64 ? h->lay : h->lay64, true, x, y);
     });
 }
 

@@ -1,6 +1,7 @@
 // C ABI: Lanczos eigensolver entry points and the converged-set selection.
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <cmath>
 #include <limits>
 
@@ -47,19 +48,36 @@ std::vector<std::pair<int, int>> select_converged(const std::vector<Cand>& cs, d
     return reps;
 }
 
-// device pointer of the FP64 start vector (uploaded into buf when given on the host)
+// device pointer of the FP64 start vector in stream order (uploaded into buf
+// when given on the host, reordered into buf when the stream order is not the
+// caller's)
 const double* start_vector(tbh::Ham& h, const tbh_lanczos_opts* o, tbh::DevBuf& buf) {
+    const size_t ns = size_t(h.dim) * (h.cplx_h ? 2 : 1);
+    const size_t row = size_t(h.n_o) * (h.cplx_h ? 2 : 1) * sizeof(double);
+    hipStream_t st = h.ctx->stream;
     if (!o->v0) {
         TBH_REQUIRE(o->v0_dev, "null start vector (v0 and v0_dev)");
-        return o->v0_dev;
+        if (!h.permuted) return o->v0_dev;
+        buf.alloc(ns * sizeof(double));
+        tbh::rows_to_stream(st, h.n, h.perm_d.as<int64_t>(), row, o->v0_dev, buf.p);
+        return buf.as<double>();
     }
     const double* v0 = o->v0;
-    const size_t ns = size_t(h.dim) * (h.cplx_h ? 2 : 1);
     double nrm = 0.0;
     for (size_t i = 0; i < ns; ++i) nrm += v0[i] * v0[i];
     TBH_REQUIRE(nrm > 0.0 && std::isfinite(nrm), "start vector is zero or not finite");
+    if (!h.permuted) {
+        buf.alloc(ns * sizeof(double));
+        TBH_HIP(hipMemcpyAsync(buf.p, v0, ns * sizeof(double), hipMemcpyHostToDevice, st));
+        return buf.as<double>();
+    }
+    std::vector<double> v(ns);
+    const size_t rd = row / sizeof(double);
+    for (int64_t k = 0; k < h.n; ++k)
+        std::memcpy(&v[size_t(k) * rd], v0 + size_t(h.perm_h[size_t(k)]) * rd, row);
     buf.alloc(ns * sizeof(double));
-    TBH_HIP(hipMemcpyAsync(buf.p, v0, ns * sizeof(double), hipMemcpyHostToDevice, h.ctx->stream));
+    TBH_HIP(hipMemcpyAsync(buf.p, v.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
+    TBH_HIP(hipStreamSynchronize(st));   // v is a local
     return buf.as<double>();
 }
 
@@ -141,9 +159,14 @@ int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, doubl
                 if (res) res[t] = c.res;
                 if (copies) copies[t] = reps[t].second;
                 mres = std::max(mres, c.res);
-                if (evecs_dev)
-                    tbh::scale_copy(st, int64_t(ns), R.Y.as<double>() + size_t(c.c) * ns, 1.0 / c.ynorm,
-                                    evecs_dev + size_t(t) * ns);
+                if (evecs_dev) {
+                    const double* y = R.Y.as<double>() + size_t(c.c) * ns;
+                    if (h->permuted)
+                        tbh::rows_to_caller_f64(st, h->n, h->perm_d.as<int64_t>(), h->n_o * (h->cplx_h ? 2 : 1),
+                                                1.0 / c.ynorm, y, evecs_dev + size_t(t) * ns);
+                    else
+                        tbh::scale_copy(st, int64_t(ns), y, 1.0 / c.ynorm, evecs_dev + size_t(t) * ns);
+                }
             } else {
                 if (evals) evals[t] = nan;
                 if (refined) refined[t] = nan;

@@ -16,10 +16,12 @@
 // iteration.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <limits>
 
 #include "lanczos.h"
 #include "scf.h"
+
 #include "tbh_internal.h"
 
 namespace tbh {
@@ -399,14 +401,18 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     TBH_REQUIRE(o.n_donors >= 0 && (o.n_donors == 0 || o.donor_atoms), "bad donor list");
     TBH_REQUIRE(o.v0, "null start vector");
     n_nodes = int64_t(grid[0]) * grid[1] * grid[2];
-    // atom -> node
+    // atom -> node, for the atoms in the ham's stream order (per-atom data
+    // inside the loop lives in that order)
     std::vector<int64_t> node(h->n);
     TBH_REQUIRE(!h->pos_h.empty(), "ham has no positions");
     std::vector<char> seen(n_nodes, 0);
-    for (int64_t i = 0; i < h->n; ++i) {
-        const int32_t* q = &h->pos_h[3 * i];
+    auto node_of = [&](int64_t caller_atom) {
+        const int32_t* q = &h->pos_h[3 * caller_atom];
         TBH_REQUIRE(q[0] < grid[0] && q[1] < grid[1] && q[2] < grid[2], "atom outside the Poisson grid");
-        node[i] = (int64_t(q[2]) * grid[1] + q[1]) * grid[0] + q[0];
+        return (int64_t(q[2]) * grid[1] + q[1]) * grid[0] + q[0];
+    };
+    for (int64_t i = 0; i < h->n; ++i) {
+        node[i] = node_of(h->caller(i));
         seen[node[i]] = 1;
     }
     node_d.alloc(h->n * 8);
@@ -416,9 +422,9 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     const double scale = 1.0 / (o.h_nm * o.h_nm * o.h_nm * EPS0_E_PER_V_NM * o.eps_r);
     std::vector<double> b0(n_nodes, 0.0);
     for (int d = 0; d < o.n_donors; ++d) {
-        const int32_t a = o.donor_atoms[d];
+        const int32_t a = o.donor_atoms[d];   // caller's atom index
         TBH_REQUIRE(a >= 0 && a < h->n, "donor atom index out of range");
-        b0[node[a]] += scale;
+        b0[node_of(a)] += scale;
     }
     b0_d.alloc(n_nodes * 8);
     TBH_HIP(hipMemcpy(b0_d.p, b0.data(), n_nodes * 8, hipMemcpyHostToDevice));
@@ -431,7 +437,15 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     Ua.alloc(h->n * 8);
     const size_t ns = size_t(h->dim) * (h->cplx_h ? 2 : 1);
     v0.alloc(ns * 8);
-    TBH_HIP(hipMemcpy(v0.p, o.v0, ns * 8, hipMemcpyHostToDevice));
+    if (h->permuted) {
+        const size_t rd = size_t(h->n_o) * (h->cplx_h ? 2 : 1);
+        std::vector<double> v(ns);
+        for (int64_t k = 0; k < h->n; ++k)
+            std::memcpy(&v[size_t(k) * rd], o.v0 + size_t(h->perm_h[size_t(k)]) * rd, rd * sizeof(double));
+        TBH_HIP(hipMemcpy(v0.p, v.data(), ns * 8, hipMemcpyHostToDevice));
+    } else {
+        TBH_HIP(hipMemcpy(v0.p, o.v0, ns * 8, hipMemcpyHostToDevice));
+    }
     part.alloc(size_t(std::max<int64_t>(2 * 4096, int64_t(o.n_cand) * 4096)) * 8);
     occ.alloc(size_t(o.n_cand) * 8);
     q.alloc(size_t(o.n_cand) * 8);

@@ -115,8 +115,13 @@ struct Layout {
     int64_t bytes = 0;
 };
 Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
-// Pack atoms into the layout (T = float or double).
-void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst);
+// Pack atoms into the layout (T = float or double); slot k of the stream
+// holds caller atom perm[k] (perm null: k).
+void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst, const int64_t* perm = nullptr);
+// Stream order of the atoms: by diamond basis class (position mod 4), then
+// conventional cell (z, y, x), stable.  Returns perm (stream slot -> caller
+// atom), or an empty vector when the caller's order already is that order.
+std::vector<int64_t> locality_order(const int32_t* pos_q, int64_t n);
 // Atom-major FP32 copy for the multi-vector kernels: per atom [5][n_o][n_o]
 // (bond slots 0..3, on-site), complex interleaved, padded to stride floats.
 void pack_atom_major(const HostModel& m, int64_t stride, float* dst);
@@ -141,8 +146,29 @@ struct Ham {
     std::vector<int8_t> wrap_h;
     std::vector<int32_t> pos_h;   // [n][3] positions (a/4 units)
     std::shared_ptr<LzWork> lz;   // Lanczos workspace kept between calls
+    // The packed stream, nbr_d, pot_d and every vector inside the library
+    // (Lanczos basis, SCF states) use the stream order; the caller's atom
+    // order is restored at the boundary (tbh_apply_h*, start vectors, Ritz
+    // vectors, potentials).  perm_h: stream slot -> caller atom.
+    bool permuted = false;
+    std::vector<int64_t> perm_h;
+    DevBuf perm_d, xs, ys;        // device perm; staging vectors of tbh_apply_h*
+    int64_t caller(int64_t k) const { return permuted ? perm_h[size_t(k)] : k; }
     int64_t hx_bytes() const;
 };
+
+// ---------------------------------------------------------------------------
+// caller order <-> stream order (order.hip)
+// ---------------------------------------------------------------------------
+// dst[k] = src[perm[k]] for rows of row_bytes (a multiple of 4)
+void rows_to_stream(hipStream_t st, int64_t n, const int64_t* perm_d, size_t row_bytes, const void* src,
+                    void* dst);
+// dst[perm[k]] = scale * src[k] for rows of row_doubles FP64 values
+void rows_to_caller_f64(hipStream_t st, int64_t n, const int64_t* perm_d, int row_doubles, double scale,
+                        const double* src, double* dst);
+// dst[perm[k]] = src[k] for rows of row_bytes (a multiple of 4)
+void rows_to_caller(hipStream_t st, int64_t n, const int64_t* perm_d, size_t row_bytes, const void* src,
+                    void* dst);
 
 struct Ctx {
     int device = 0;
