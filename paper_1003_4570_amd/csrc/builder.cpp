@@ -380,15 +380,17 @@ void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t 
 }  // namespace
 
 std::vector<int64_t> locality_order(const int32_t* q, int64_t n) {
-    // With this order the atoms of one basis class along a row of cells are
-    // consecutive, and so are their neighbours in any one bond direction
-    // (each is one fixed class of the other sublattice, one cell offset
-    // away): a wavefront's neighbour gathers then read runs of contiguous
-    // rows instead of 64 scattered ones.
+    // Rows of conventional cells (z, y) in order; within a row, the atoms of
+    // each diamond basis class (position mod 4) as a run along x.  The
+    // neighbours of such a run in any one bond direction are one fixed class
+    // of the other sublattice in the same or an adjacent row, one cell
+    // offset away: again a run of consecutive atoms.  A wavefront's neighbour
+    // gathers then read contiguous rows, and the rows it needs lie within one
+    // row of cells of its own, so an XCD's L2 holds them.
     auto key = [&](int64_t i) {
         const int32_t* p = q + 3 * i;
         const int cls = ((p[0] & 3) * 4 + (p[1] & 3)) * 4 + (p[2] & 3);
-        return std::array<int64_t, 4>{cls, p[2] >> 2, p[1] >> 2, p[0] >> 2};
+        return std::array<int64_t, 4>{p[2] >> 2, p[1] >> 2, cls, p[0] >> 2};
     };
     std::vector<int64_t> perm(static_cast<size_t>(n));
     for (int64_t i = 0; i < n; ++i) perm[size_t(i)] = i;

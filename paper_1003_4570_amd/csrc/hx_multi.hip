@@ -15,8 +15,11 @@
 // vectors are the 16-wide M dimension, the embedded output rows the N
 // dimension (two 16-wide tiles for 20 rows), K = 5 n_o (x2 for complex).
 // One wavefront owns one atom at a time: it stages the atom's five blocks
-// (4 KB for 10x10 complex) into LDS with 16-byte loads, reads its B-operand
-// from LDS and gathers the X rows of the neighbours straight from L2.
+// (4 KB for 10x10 complex) into LDS, reads its B-operand from LDS and
+// gathers the X rows of the neighbours straight from L2, every gather of the
+// atom in flight at once.  The next atom's blocks and neighbour indices are
+// loaded into registers (16-byte non-temporal loads) while the current
+// atom's products run.
 // A persistent grid walks the concatenated atom range in contiguous chunks,
 // mapped XCD-contiguously so that one XCD's L2 holds the X rows its
 // neighbouring atoms share.
@@ -46,6 +49,9 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
     constexpr int MT = NRHS / 16;               // M tiles (right-hand vectors)
     constexpr int BF = 5 * NO * NO * CS;        // block floats per atom
     constexpr int BFP = (BF + 3) & ~3;          // padded to 16 bytes
+    constexpr int NV = BFP / 4;                 // 16-byte chunks per atom
+    constexpr int PV = (NV + 63) / 64;          // chunks per lane
+    constexpr int DIAG0 = 4 * NO * NO * CS;     // first on-site float
     __shared__ float blk[BFP];
 
     const int lane = threadIdx.x;
@@ -60,42 +66,97 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
     int inst = 0;
     while (inst + 1 < n_inst && desc[inst + 1].atom_begin <= g) ++inst;
 
+    // software pipeline: the next atom's blocks and neighbour indices are
+    // loaded into registers while the current atom's products run
+    v4f pre[PV];
+    int32_t pnb[4];
+    auto prefetch = [&](int ins, int64_t gg) {
+        const MvDesc& d = desc[ins];
+        const int64_t at = gg - d.atom_begin;
+        const v4f* src = reinterpret_cast<const v4f*>(d.blocks + at * BFP);
+#pragma unroll
+        for (int p = 0; p < PV; ++p) {
+            const int c = lane + p * 64;
+            if (c < NV) pre[p] = __builtin_nontemporal_load(src + c);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) pnb[s] = d.nbr[at * 4 + s];
+    };
+    prefetch(inst, g);
+
     for (; g < g_end; ++g) {
-        while (g >= desc[inst].atom_begin + desc[inst].n_atoms) ++inst;
         const MvDesc& d = desc[inst];
         const int64_t atom = g - d.atom_begin;
-        // stage the five blocks (bonds 0..3, on-site) into LDS
-        const v4f* src = reinterpret_cast<const v4f*>(d.blocks + atom * BFP);
-        for (int c = lane; c < BFP / 4; c += 64) reinterpret_cast<v4f*>(blk)[c] = src[c];
-        __syncthreads();
-        if (d.pot && lane < NO) blk[((4 * NO + lane) * NO + lane) * CS] += float(d.pot[atom]);
-        __syncthreads();
-        int64_t nb[5];
+        // stage the prefetched blocks (bonds 0..3, on-site + potential on its
+        // diagonal) into LDS
+        const float u = d.pot ? float(d.pot[atom]) : 0.f;
+#pragma unroll
+        for (int p = 0; p < PV; ++p) {
+            const int c = lane + p * 64;
+            if (c < NV) {
+                v4f v = pre[p];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int f = c * 4 + e - DIAG0;                 // on-site float index
+                    if (f >= 0 && f < NO * NO * CS && (f / CS) % (NO + 1) == 0 && f % CS == 0) v[e] += u;
+                }
+                reinterpret_cast<v4f*>(blk)[c] = v;
+            }
+        }
+        // neighbour rows of X (wave-uniform: one atom per wavefront)
+        const float* __restrict__ X = d.x;
+        const float* xb[5];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int32_t j = d.nbr[atom * 4 + s];
-            nb[s] = j >= 0 ? j : atom;   // dangling: the staged block is zero
+            const int32_t j = __builtin_amdgcn_readfirstlane(pnb[s]);
+            xb[s] = X + (j >= 0 ? int64_t(j) : atom) * (NO * NRHS * CS);   // dangling: the block is zero
         }
-        nb[4] = atom;
-        const float* __restrict__ X = d.x;
+        xb[4] = X + atom * (NO * NRHS * CS);
+        __syncthreads();
+        // the right-hand-side gathers of this atom, all in flight at once
+        const int kl = lane >> 4, col = lane & 15;
+        float a[KS][MT];
+        if constexpr (CPLX && NO % 2 == 0) {
+            // k = 4 ks + kl: part p = kl & 1, column c = 2 ks % NO + kl / 2,
+            // slot s = 2 ks / NO (the same for all lanes since NO is even)
+            const int lane_off = ((kl >> 1) * NRHS + col) * 2 + (kl & 1);
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int s = (2 * ks) / NO, c0 = (2 * ks) % NO;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a[ks][mt] = xb[s][lane_off + (c0 * NRHS + mt * 16) * 2];
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = ks * 4 + kl;
+                const int kk = k < KE ? k : 0;
+                const int p = CPLX ? (kk & 1) : 0;
+                const int sc = CPLX ? (kk >> 1) : kk;
+                const int s = sc / NO, c = sc % NO;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    a[ks][mt] = k < KE ? xb[s][((c * NRHS) + mt * 16 + col) * CS + p] : 0.f;
+            }
+        }
+        // next atom's blocks
+        if (g + 1 < g_end) {
+            int ins = inst;
+            while (g + 1 >= desc[ins].atom_begin + desc[ins].n_atoms) ++ins;
+            prefetch(ins, g + 1);
+        }
         v4f acc[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
-        const int kl = lane >> 4, col = lane & 15;
-#pragma unroll 5
+#pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int k = ks * 4 + kl;
-            // decode k -> (slot s, column c, input part p)
             const int kk = k < KE ? k : 0;
             const int p = CPLX ? (kk & 1) : 0;
             const int sc = CPLX ? (kk >> 1) : kk;
             const int s = sc / NO, c = sc % NO;
-            float a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                a[mt] = k < KE ? X[((nb[s] * NO + c) * NRHS + mt * 16 + col) * CS + p] : 0.f;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int m = t * 16 + col;
@@ -112,7 +173,7 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
                 }
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
-                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mt], b, acc[mt][t], 0, 0, 0);
+                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][mt], b, acc[mt][t], 0, 0, 0);
             }
         }
         // D[i = 4*(lane/16) + v][j = lane%16] = Y^T[rhs][m]
@@ -132,7 +193,9 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
                     }
                 }
             }
+        // every lane's LDS reads are done before the next atom overwrites blk
         __syncthreads();
+        while (g + 1 < g_end && g + 1 >= desc[inst].atom_begin + desc[inst].n_atoms) ++inst;
     }
 }
 

@@ -118,9 +118,10 @@ Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool 
 // Pack atoms into the layout (T = float or double); slot k of the stream
 // holds caller atom perm[k] (perm null: k).
 void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst, const int64_t* perm = nullptr);
-// Stream order of the atoms: by diamond basis class (position mod 4), then
-// conventional cell (z, y, x), stable.  Returns perm (stream slot -> caller
-// atom), or an empty vector when the caller's order already is that order.
+// Stream order of the atoms: by row of conventional cells (z, y), then
+// diamond basis class (position mod 4), then x, stable.  Returns perm
+// (stream slot -> caller atom), or an empty vector when the caller's order
+// already is that order.
 std::vector<int64_t> locality_order(const int32_t* pos_q, int64_t n);
 // Atom-major FP32 copy for the multi-vector kernels: per atom [5][n_o][n_o]
 // (bond slots 0..3, on-site), complex interleaved, padded to stride floats.
