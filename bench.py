@@ -45,7 +45,8 @@ ITERS_PER_STEP = 500
 
 def _kernel_hash():
     h = hashlib.sha256()
-    for f in ("hx.hip", "tbh_internal.h"):
+    # the kernel, its layout, and the builder (which fixes the atom order)
+    for f in ("hx.hip", "tbh_internal.h", "builder.cpp"):
         with open(os.path.join(ROOT, "paper_1003_4570_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -96,8 +96,11 @@ class Study:
         ub = (self.bare_potential(dmap) / feat_scale).float()
         return torch.stack([d, self._masks[0], self._masks[1], ub]).contiguous()
 
-    def surrogate(self, weights):
-        """Load trained weights; returns start(dmap) -> device FP64 [nz, ny, nx]."""
+    def surrogate(self, weights, symmetrize_output=True):
+        """Load trained weights; returns start(dmap) -> device FP64 [nz, ny, nx].
+        With symmetrize_output the network's output is averaged over the
+        in-plane point operations of the slab (point_ops): each is applied
+        to the input maps, the output mapped back, and the four averaged."""
         wz = np.load(weights)
         nz, ny, nx = wz["Tbar"].shape
         dil = tuple(int(d) for d in wz["dilations"]) if "dilations" in wz.files else (1, 2, 4, 1)
@@ -107,7 +110,12 @@ class Study:
         scale, fs, target = float(wz["scale"]), float(wz["feat_scale"]), str(wz["target"])
 
         def start(dmap):
-            u = Tbar + scale * net.forward(self.inputs(dmap, fs)).double()
+            x = self.inputs(dmap, fs)
+            if symmetrize_output:
+                y = sum(inv(net.forward(op(x).contiguous())) for op, inv in point_ops()) / 4.0
+            else:
+                y = net.forward(x)
+            u = Tbar + scale * y.double()
             return u + self.bare_potential(dmap) if target == "E" else u
         start.Tbar = Tbar
         start.target = target
@@ -219,6 +227,30 @@ def lattice_shifts(grid):
     by 4 (generated by the fcc vectors (2, 2, 0) and (4, 0, 0))."""
     nx, ny, _ = grid
     return [(sx, sy) for sy in range(0, ny, 2) for sx in range(0, nx, 2) if (sx + sy) % 4 == 0]
+
+
+def point_ops():
+    """The in-plane point operations that map the diamond slab onto itself
+    (its two sublattices each onto itself): identity, the (110) mirror
+    (x, y) -> (y, x), the (1-10) mirror (x, y) -> (-y, -x) and their product,
+    the two-fold rotation (x, y) -> (-x, -y), all about the atom at the
+    origin, on maps whose last two axes are (y, x).  Pairs (op, inverse);
+    each is its own inverse."""
+    import torch
+
+    def ident(a):
+        return a
+
+    def mirror(a):
+        return a.transpose(-1, -2)
+
+    def rot2(a):
+        return torch.roll(torch.flip(a, dims=(-1, -2)), shifts=(1, 1), dims=(-2, -1))
+
+    def antimirror(a):
+        return rot2(a).transpose(-1, -2)
+
+    return [(ident, ident), (mirror, mirror), (antimirror, antimirror), (rot2, rot2)]
 
 
 def symmetrize(a, grid):

@@ -154,3 +154,26 @@ def test_lattice_shifts_are_symmetries_of_the_study_slab():
     for sx, sy in sh:
         assert np.allclose(np.roll(s, (sy, sx), axis=(-2, -1)), s)
     assert np.isclose(s.mean(), a.mean())
+
+
+def test_point_ops_are_symmetries_of_the_study_slab():
+    """The in-plane point operations averaged over by the surrogate map the
+    study slab's atoms and its donor-plane sites onto themselves (each
+    sublattice onto itself) and are involutions."""
+    import torch
+    from paper_1003_4570_amd import surrogate as S
+    p = W.study_slab(0)
+    g = p.extra["grid"]
+    m = torch.from_numpy(W.sublattice_masks(p.pos_q, g))
+    plane = torch.zeros_like(m[0])
+    for s in range(60):
+        d = W.donor_map(W.study_slab(s).pos_q, W.study_slab(s).extra["donor_atoms"], g)
+        plane += torch.from_numpy(d > 0).float()
+    sites = plane > 0
+    ops = S.point_ops()
+    assert len(ops) == 4
+    a = torch.randn(3, g[2], g[1], g[0], dtype=torch.float64)
+    for op, inv in ops:
+        assert torch.equal(op(m), m)
+        assert torch.equal(op(sites), sites)
+        assert torch.equal(inv(op(a)), a)
