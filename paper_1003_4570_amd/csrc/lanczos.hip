@@ -8,7 +8,7 @@
 //   hx (fused):  w = H v_j - beta_j v_{j-1}, FP64 partials of Re(v_j^H w), |w|^2
 //   scalars:     alpha_j; without reorthogonalisation beta_{j+1}^2 =
 //                |w|^2 - alpha_j^2 (guarded: on cancellation the norm of
-//                w - alpha_j v_j is taken explicitly)
+//                w - alpha_j v_j is taken explicitly, in the same kernel)
 //   CGS2:        w -= alpha_j v_j, then twice { c = V^H w ; w -= V c } with
 //                FP64 accumulation over FP32 (or FP64) stored vectors
 //   next:        v_{j+1} = w / beta_{j+1}; breakdown if beta_{j+1} <= 1e-12 max|T|
@@ -62,15 +62,29 @@ __device__ double block_reduce_strided(const double* part, int64_t n, int stride
 // step scalars
 // ---------------------------------------------------------------------------
 
-// After the fused hx kernel: alpha_j and (without reorthogonalisation) the
-// beta_{j+1} shortcut.  The hx kernel leaves one (Re x^H y, |y|^2) pair per
+// After the fused hx kernel: alpha_j and (without reorthogonalisation)
+// beta_{j+1}.  The hx kernel leaves one (Re x^H y, |y|^2) pair per
 // wavefront (16k pairs for a million atoms); one 1024-thread block sums both
 // in a single pass of 16-byte loads with four independent accumulators per
-// thread, in a fixed order.
+// thread, in a fixed order.  beta_{j+1}^2 = |w|^2 - alpha_j^2 unless that
+// cancels (below 1e-8 |w|^2); then the same block takes |w - alpha_j v_j|
+// explicitly over the n scalars of w and v_j (slow, and only on that path).
 constexpr int SCAL_TPB = 1024;
 
+__device__ __forceinline__ double scal_block_sum(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int w = 0; w < SCAL_TPB / 64; ++w) r += sh[w];
+    return r;
+}
+
+template <typename T>
 __global__ __launch_bounds__(SCAL_TPB) void k_step_scalars(const double* part, int64_t nblk, LzDev d, int j,
-                                                           int reorth) {
+                                                           int reorth, const T* w, const T* vj, int64_t n) {
     if (d.ctrl[LZ_BREAK] != 0.0) return;
     typedef double d2 __attribute__((ext_vector_type(2)));
     const d2* p = reinterpret_cast<const d2*>(part);
@@ -85,49 +99,47 @@ __global__ __launch_bounds__(SCAL_TPB) void k_step_scalars(const double* part, i
     }
     for (; b < nblk; b += SCAL_TPB) s0 += p[b];
     const d2 t = (s0 + s1) + (s2 + s3);
-    double sa = t.x, sw = t.y;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        sa += __shfl_xor(sa, off, 64);
-        sw += __shfl_xor(sw, off, 64);
-    }
-    __shared__ double sh[SCAL_TPB / 64][2];
-    if ((threadIdx.x & 63) == 0) {
-        sh[threadIdx.x >> 6][0] = sa;
-        sh[threadIdx.x >> 6][1] = sw;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double a = 0.0, ww = 0.0;
-    for (int w = 0; w < SCAL_TPB / 64; ++w) {
-        a += sh[w][0];
-        ww += sh[w][1];
-    }
-    d.alpha[j] = a;
-    d.ctrl[LZ_TMAX] = fmax(d.ctrl[LZ_TMAX], fabs(a));
-    if (reorth) return;
-    const double b2 = ww - a * a;
-    if (b2 > 1e-8 * ww) {
-        const double bb = sqrt(b2);
-        d.beta[j + 1] = bb;
-        d.ctrl[LZ_FLAG] = 0.0;
-        d.ctrl[LZ_TMAX] = fmax(d.ctrl[LZ_TMAX], bb);
-        if (bb <= 1e-12 * d.ctrl[LZ_TMAX]) {
-            d.ctrl[LZ_BREAK] = 1.0;
-        } else {
-            d.ctrl[LZ_INVB] = 1.0 / bb;
+    __shared__ double sh[SCAL_TPB / 64];
+    // every thread holds the block totals, so the branch below is uniform
+    const double a = scal_block_sum(t.x, sh);
+    const double ww = scal_block_sum(t.y, sh);
+    const double tmax = fmax(d.ctrl[LZ_TMAX], fabs(a));
+    if (reorth) {
+        if (threadIdx.x == 0) {
+            d.alpha[j] = a;
+            d.ctrl[LZ_TMAX] = tmax;
         }
-        d.ctrl[LZ_STEPS] = j + 1;
+        return;
+    }
+    const double b2 = ww - a * a;
+    double bb;
+    if (b2 > 1e-8 * ww) {
+        bb = sqrt(b2);
     } else {
-        d.ctrl[LZ_FLAG] = 1.0;  // cancellation: norm taken explicitly
+        // cancellation: the norm of w - alpha_j v_j, explicitly
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += SCAL_TPB) {
+            const double u = double(w[i]) - a * double(vj[i]);
+            acc += u * u;
+        }
+        bb = sqrt(scal_block_sum(acc, sh));
+    }
+    if (threadIdx.x != 0) return;
+    d.alpha[j] = a;
+    d.beta[j + 1] = bb;
+    const double tm = fmax(tmax, bb);
+    d.ctrl[LZ_TMAX] = tm;
+    d.ctrl[LZ_STEPS] = j + 1;
+    if (bb <= 1e-12 * tm) {
+        d.ctrl[LZ_BREAK] = 1.0;
+    } else {
+        d.ctrl[LZ_INVB] = 1.0 / bb;
     }
 }
 
-// beta_{j+1} = sqrt(sum of explicit |w|^2 partials); when only_flagged, runs
-// only if the shortcut was rejected.
-__global__ void k_finish_beta(const double* part, int64_t nblk, LzDev d, int j, int only_flagged) {
+// beta_{j+1} = sqrt(sum of explicit |w|^2 partials) (reorthogonalised path)
+__global__ void k_finish_beta(const double* part, int64_t nblk, LzDev d, int j) {
     if (d.ctrl[LZ_BREAK] != 0.0) return;
-    if (only_flagged && d.ctrl[LZ_FLAG] == 0.0) return;
     const double s = block_reduce_strided(part, nblk, 1, 0);
     if (threadIdx.x != 0) return;
     const double b = sqrt(s);
@@ -145,35 +157,20 @@ __global__ void k_finish_beta(const double* part, int64_t nblk, LzDev d, int j, 
 // vector kernels (n = number of real scalars; complex vectors interleaved)
 // ---------------------------------------------------------------------------
 
-// no reorthogonalisation: v_{j+1} = (w - alpha_j v_j) / beta_{j+1}, or on the
-// flagged path u = w - alpha_j v_j written to w with |u|^2 partials.
+// no reorthogonalisation: v_{j+1} = (w - alpha_j v_j) / beta_{j+1}
 template <typename T>
-__global__ void k_lz_next(int64_t n, T* w, const T* vj, T* vn, LzDev d, int j, double* part) {
-    if (d.ctrl[LZ_BREAK] != 0.0 && d.ctrl[LZ_FLAG] == 0.0) return;
-    const bool flagged = d.ctrl[LZ_FLAG] != 0.0;
+__global__ void k_lz_next(int64_t n, const T* w, const T* vj, T* vn, LzDev d, int j) {
+    if (d.ctrl[LZ_BREAK] != 0.0) return;
     const double a = d.alpha[j];
-    double acc[1] = {0.0};
-    if (!flagged) {
-        const double ib = d.ctrl[LZ_INVB];
-        for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
-            vn[i] = T((double(w[i]) - a * double(vj[i])) * ib);
-        return;
-    }
-    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
-        const T u = T(double(w[i]) - a * double(vj[i]));
-        w[i] = u;
-        acc[0] += double(u) * double(u);
-    }
-    __shared__ double sh[4][1];
-    block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    const double ib = d.ctrl[LZ_INVB];
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+        vn[i] = T((double(w[i]) - a * double(vj[i])) * ib);
 }
 
-// v_{j+1} = w * (1/beta_{j+1}); when only_flagged, runs only on the flagged path
+// v_{j+1} = w * (1/beta_{j+1}) (reorthogonalised path)
 template <typename T>
-__global__ void k_scale_next(int64_t n, const T* w, T* vn, LzDev d, int only_flagged) {
+__global__ void k_scale_next(int64_t n, const T* w, T* vn, LzDev d) {
     if (d.ctrl[LZ_BREAK] != 0.0) return;
-    if (only_flagged && d.ctrl[LZ_FLAG] == 0.0) return;
     const double ib = d.ctrl[LZ_INVB];
     for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
         vn[i] = T(double(w[i]) * ib);
@@ -606,21 +603,19 @@ void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j], st));
         hx_launch(h.lay, f64, a, st);
         if (ev) TBH_HIP(hipEventRecord((*ev)[2 * j + 1], st));
-        hipLaunchKernelGGL(k_step_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, nblk_hx, d, j, int(reorth));
+        if (f64)
+            hipLaunchKernelGGL(k_step_scalars<double>, dim3(1), dim3(SCAL_TPB), 0, st, part, nblk_hx, d, j,
+                               int(reorth), W.w.as<double>(), static_cast<const double*>(vj), ns);
+        else
+            hipLaunchKernelGGL(k_step_scalars<float>, dim3(1), dim3(SCAL_TPB), 0, st, part, nblk_hx, d, j,
+                               int(reorth), W.w.as<float>(), static_cast<const float*>(vj), ns);
         if (!reorth) {
-            if (f64) {
+            if (f64)
                 hipLaunchKernelGGL(k_lz_next<double>, dim3(gv), dim3(TPB), 0, st, ns, W.w.as<double>(),
-                                   static_cast<const double*>(vj), static_cast<double*>(vn), d, j, part);
-                hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(TPB), 0, st, part, gv, d, j, 1);
-                hipLaunchKernelGGL(k_scale_next<double>, dim3(gv), dim3(TPB), 0, st, ns,
-                                   W.w.as<double>(), static_cast<double*>(vn), d, 1);
-            } else {
+                                   static_cast<const double*>(vj), static_cast<double*>(vn), d, j);
+            else
                 hipLaunchKernelGGL(k_lz_next<float>, dim3(gv), dim3(TPB), 0, st, ns, W.w.as<float>(),
-                                   static_cast<const float*>(vj), static_cast<float*>(vn), d, j, part);
-                hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(TPB), 0, st, part, gv, d, j, 1);
-                hipLaunchKernelGGL(k_scale_next<float>, dim3(gv), dim3(TPB), 0, st, ns,
-                                   W.w.as<float>(), static_cast<float*>(vn), d, 1);
-            }
+                                   static_cast<const float*>(vj), static_cast<float*>(vn), d, j);
             const int t = iprev;
             iprev = icur;
             icur = inext;
@@ -629,10 +624,10 @@ void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
             orth_cgs2(h, W, d, j, st);
             if (f64)
                 hipLaunchKernelGGL(k_scale_next<double>, dim3(gv), dim3(TPB), 0, st, ns,
-                                   W.w.as<double>(), static_cast<double*>(vn), d, 0);
+                                   W.w.as<double>(), static_cast<double*>(vn), d);
             else
                 hipLaunchKernelGGL(k_scale_next<float>, dim3(gv), dim3(TPB), 0, st, ns,
-                                   W.w.as<float>(), static_cast<float*>(vn), d, 0);
+                                   W.w.as<float>(), static_cast<float*>(vn), d);
         }
     }
     TBH_HIP(hipGetLastError());
@@ -743,7 +738,7 @@ void orth_cgs2(Ham& h, LzWork& W, const LzDev& d, int j, hipStream_t st) {
         }
 #undef TBH_ORTH
     }
-    hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(TPB), 0, st, part, gu, d, j, 0);
+    hipLaunchKernelGGL(k_finish_beta, dim3(1), dim3(TPB), 0, st, part, gu, d, j);
 }
 
 void tridiag_gpu(hipStream_t st, int m, const double* alpha_d, const double* beta_d, double* theta_d) {

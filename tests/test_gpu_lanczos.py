@@ -167,6 +167,26 @@ def test_breakdown_on_eigenvector(ctx):
     assert rep["breakdown"] == 1 and rep["steps"] == 1
 
 
+def test_cancellation_guard_without_reorth(ctx):
+    """A start vector within 1e-7 of the eigenvector of largest |lambda|
+    makes |w|^2 - alpha^2 cancel to 3e-13 of |w|^2; the guard then takes
+    |w - alpha v| explicitly, so beta_1 matches the oracle's explicit norm to
+    1e-6 relative (the shortcut would be off by 4.5e-4)."""
+    p = W.problem_periodic_cube(1, seed=5, model=W.MODEL_SP3S, strain=True, potential=0.5)
+    H = T.hamiltonian(p).toarray()
+    w, U = np.linalg.eigh(H)
+    k = int(np.argmax(np.abs(w)))
+    v0 = U[:, k] + 1e-7 * np.random.default_rng(3).standard_normal(p.dim)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64"))
+    a, b, rep = tbh.lanczos_run(h, 4, v0, reorth=False)
+    ao, bo, _ = L.lanczos(lambda x: H @ x, v0, 4, reorth=False)
+    assert rep["breakdown"] == 0 and rep["steps"] == 4
+    assert abs(a[0] - ao[0]) < 1e-12
+    assert abs(b[0] - bo[0]) <= 1e-6 * bo[0]
+    assert bo[0] < 1e-5 * abs(ao[0])
+    assert np.abs(a[1:] - ao[1:]).max() < 1e-6
+
+
 def test_fp32_pipeline_hardwall_so(ctx):
     """C2 recipe (sp3d5s* + SO, hard wall, +30 eV passivation, strain) on a
     3^3 cube: FP32 H.x and vectors, FP64 scalars; refined values against the
