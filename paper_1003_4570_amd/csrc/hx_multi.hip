@@ -20,9 +20,9 @@
 // atom in flight at once.  The next atom's blocks and neighbour indices are
 // loaded into registers (16-byte non-temporal loads) while the current
 // atom's products run.
-// A persistent grid walks the concatenated atom range in contiguous chunks,
-// mapped XCD-contiguously so that one XCD's L2 holds the X rows its
-// neighbouring atoms share.
+// A persistent grid walks the concatenated atom range with a grid stride,
+// workgroups mapped XCD-contiguously, so that the atoms in flight form one
+// window and one XCD's L2 holds the X rows its neighbouring atoms share.
 #include "tbh_internal.h"
 #include "hx_multi.h"
 
@@ -40,7 +40,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblk, int rema
 
 template <bool CPLX, int NO, int NRHS>
 __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, int n_inst, int64_t total,
-                                              int64_t chunk, int remap) {
+                                              int remap) {
     constexpr int CS = CPLX ? 2 : 1;
     constexpr int ME = NO * CS;                 // embedded output rows
     constexpr int KE = 5 * NO * CS;             // embedded K
@@ -59,8 +59,12 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
     // the table may be a slice of a larger batch: its atom range starts at
     // desc[0].atom_begin and spans `total` atoms
     const int64_t base = desc[0].atom_begin;
-    int64_t g = base + lb * chunk;
-    const int64_t g_end = g + chunk < base + total ? g + chunk : base + total;
+    // grid-stride walk: at any moment the wavefronts in flight hold one
+    // window of `gridDim.x` consecutive atoms (each XCD a contiguous part
+    // of it), so the X rows their neighbours share stay in L2
+    const int64_t step = gridDim.x;
+    int64_t g = base + lb;
+    const int64_t g_end = base + total;
     if (g >= g_end) return;
     // instance containing g
     int inst = 0;
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
     };
     prefetch(inst, g);
 
-    for (; g < g_end; ++g) {
+    for (; g < g_end; g += step) {
         const MvDesc& d = desc[inst];
         const int64_t atom = g - d.atom_begin;
         // stage the prefetched blocks (bonds 0..3, on-site + potential on its
@@ -140,40 +144,73 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
             }
         }
         // next atom's blocks
-        if (g + 1 < g_end) {
+        if (g + step < g_end) {
             int ins = inst;
-            while (g + 1 >= desc[ins].atom_begin + desc[ins].n_atoms) ++ins;
-            prefetch(ins, g + 1);
+            while (g + step >= desc[ins].atom_begin + desc[ins].n_atoms) ++ins;
+            prefetch(ins, g + step);
         }
         v4f acc[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[mt][t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int k = ks * 4 + kl;
-            const int kk = k < KE ? k : 0;
-            const int p = CPLX ? (kk & 1) : 0;
-            const int sc = CPLX ? (kk >> 1) : kk;
-            const int s = sc / NO, c = sc % NO;
+        if constexpr (CPLX && NO % 2 == 0) {
+            // B operand of output row m = 16 t + col, K index k = 4 ks + kl:
+            // block float ((s NO + r) NO + c) 2 + q with s = 2 ks / NO,
+            // c = 2 ks % NO + kl / 2 and a row part r, part q and sign fixed
+            // per lane and tile, so every read is one lane base plus a
+            // constant offset
+            const int p = kl & 1, hh = kl >> 1;
+            int bofs[NT];
+            float sgn[NT];
+            bool ok[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int m = t * 16 + col;
-                float b = 0.f;
-                if (k < KE && m < ME) {
-                    if constexpr (CPLX) {
-                        const int r = m < NO ? m : m - NO;
-                        const int q = m < NO ? p : 1 - p;
-                        const float v = blk[((s * NO + r) * NO + c) * 2 + q];
-                        b = (m < NO && p == 1) ? -v : v;
-                    } else {
-                        b = blk[(s * NO + m) * NO + c];
-                    }
-                }
+                ok[t] = m < ME;
+                const int r = m < NO ? m : m - NO;
+                const int q = m < NO ? p : 1 - p;
+                sgn[t] = (m < NO && p == 1) ? -1.f : 1.f;
+                bofs[t] = ok[t] ? 2 * (r * NO + hh) + q : 0;
+            }
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][mt], b, acc[mt][t], 0, 0, 0);
+            for (int ks = 0; ks < KS; ++ks) {
+                const int s = (2 * ks) / NO, c0 = (2 * ks) % NO;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const float v = blk[bofs[t] + 2 * (s * NO * NO + c0)];
+                    const float b = ok[t] ? sgn[t] * v : 0.f;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][mt], b, acc[mt][t], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = ks * 4 + kl;
+                const int kk = k < KE ? k : 0;
+                const int p = CPLX ? (kk & 1) : 0;
+                const int sc = CPLX ? (kk >> 1) : kk;
+                const int s = sc / NO, c = sc % NO;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int m = t * 16 + col;
+                    float b = 0.f;
+                    if (k < KE && m < ME) {
+                        if constexpr (CPLX) {
+                            const int r = m < NO ? m : m - NO;
+                            const int q = m < NO ? p : 1 - p;
+                            const float v = blk[((s * NO + r) * NO + c) * 2 + q];
+                            b = (m < NO && p == 1) ? -v : v;
+                        } else {
+                            b = blk[(s * NO + m) * NO + c];
+                        }
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ks][mt], b, acc[mt][t], 0, 0, 0);
+                }
             }
         }
         // D[i = 4*(lane/16) + v][j = lane%16] = Y^T[rhs][m]
@@ -195,17 +232,16 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
             }
         // every lane's LDS reads are done before the next atom overwrites blk
         __syncthreads();
-        while (g + 1 < g_end && g + 1 >= desc[inst].atom_begin + desc[inst].n_atoms) ++inst;
+        while (g + step < g_end && g + step >= desc[inst].atom_begin + desc[inst].n_atoms) ++inst;
     }
 }
 
 template <bool CPLX, int NO>
 void launch_no(int nrhs, const MvDesc* desc, int n_inst, int64_t total, int grid, int remap, hipStream_t s) {
-    const int64_t chunk = (total + grid - 1) / grid;
     if (nrhs == 16)
-        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 16>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, chunk, remap);
+        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 16>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, remap);
     else if (nrhs == 32)
-        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 32>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, chunk, remap);
+        hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 32>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, remap);
     else
         throw Error(TBH_EINVAL, "multi-vector H.X supports nrhs = 16 or 32");
 }
