@@ -132,3 +132,30 @@ def test_hx_c3_full_size_sampled(ctx):
     ref = T.hx_rows(p, atoms, x.numpy().astype(np.float64), nbr=nbr, wrap=wrap)
     got = y.reshape(p.n_atoms, -1)[atoms]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_caller_order_does_not_matter(ctx, prec):
+    """The library renumbers atoms into its stream order internally, so the
+    same structure given with its atoms shuffled yields bitwise the same
+    H.x (rows shuffled alike) and the same Lanczos coefficients."""
+    import dataclasses
+    import torch
+    p = W.problem_periodic_cube(3, seed=4, model=W.MODEL_SP3D5S, strain=True, potential=0.4, prec=prec)
+    rng = np.random.default_rng(11)
+    perm = rng.permutation(p.n_atoms)
+    q = dataclasses.replace(p, pos_q=p.pos_q[perm], species=p.species[perm],
+                            bond_scale=None if p.bond_scale is None else p.bond_scale[perm],
+                            onsite_pot=None if p.onsite_pot is None else p.onsite_pot[perm])
+    no = p.n_orb
+    h1 = tbh.build_hamiltonian(ctx, **tbh.problem_args(p))
+    h2 = tbh.build_hamiltonian(ctx, **tbh.problem_args(q))
+    x1 = torch.from_numpy(rng.uniform(-1, 1, (p.n_atoms, no))).to(h1.torch_dtype()).cuda()
+    x2 = x1[torch.from_numpy(perm).cuda()].contiguous()
+    y1 = tbh.apply_h(h1, x1.reshape(-1)).reshape(p.n_atoms, no)
+    y2 = tbh.apply_h(h2, x2.reshape(-1)).reshape(p.n_atoms, no)
+    assert torch.equal(y1[torch.from_numpy(perm).cuda()], y2)
+    v0 = rng.uniform(-1, 1, (p.n_atoms, no))
+    a1, b1, _ = tbh.lanczos_run(h1, 60, v0.ravel(), reorth=False)
+    a2, b2, _ = tbh.lanczos_run(h2, 60, v0[perm].ravel(), reorth=False)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
