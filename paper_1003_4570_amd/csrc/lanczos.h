@@ -6,7 +6,7 @@
 namespace tbh {
 
 // control slots after alpha[m], beta[m+1]
-enum { LZ_TMAX = 0, LZ_FLAG = 1, LZ_BREAK = 2, LZ_STEPS = 3, LZ_INVB = 4, LZ_NCTRL = 8 };
+enum { LZ_TMAX = 0, LZ_BREAK = 2, LZ_STEPS = 3, LZ_INVB = 4, LZ_NCTRL = 8 };   // slot 1 unused
 
 // device view of the scalar state: alpha[j], beta[j] (beta[0] = 0, beta[j]
 // couples v_{j-1} and v_j), control slots
