@@ -223,6 +223,47 @@ def bench_c4(a):
     print(json.dumps(out), flush=True)
 
 
+def bench_c3t(a):
+    """The million-atom alloy with tabulated bond blocks (an unstrained real
+    H at Gamma has one block per sublattice, species pair and slot): time per
+    H.x and per Lanczos step against the stored-block format, 500 steps."""
+    import torch
+    import paper_1003_4570_amd as tbh
+    import workloads as W
+    prob = W.c3_alloy(0)
+    ctx = tbh.Context(0)
+    v0 = torch.tensor(prob.v0, dtype=torch.float64, device="cuda")
+    res = {}
+    for fmt in ("stored", "tabulated"):
+        print(f"bench c3t: build {fmt}", file=sys.stderr, flush=True)
+        ham = tbh.build_hamiltonian(ctx, **tbh.problem_args(prob, tabulated=(fmt == "tabulated")))
+        tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            a_, b_, _ = tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False)
+        torch.cuda.synchronize()
+        step_us = (time.perf_counter() - t0) / (3 * ITERS_PER_STEP) * 1e6
+        _, _, rep = tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False, time_hx=True)
+        hx_us = rep["hx_seconds"] / ITERS_PER_STEP * 1e6
+        # fused step bytes: the format's H.x bytes plus x_prev
+        by = ham.info["hx_bytes"] + ham.info["dim"] * 4
+        res[fmt] = dict(hx_us=hx_us, step_us=step_us, hx_bytes=by, GBs=by / (hx_us * 1e-6) / 1e9,
+                        alpha=a_, beta=b_)
+        del ham
+    st, tb = res["stored"], res["tabulated"]
+    out = {"metric": "H.x time per Lanczos step, tabulated bond blocks", "value": round(tb["hx_us"], 2),
+           "unit": "us", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "lanczos500_si0.7ge0.3_51x51x51_sp3d5s_fp32_tabulated", "atoms": prob.n_atoms},
+           "extra": {"stored_hx_us": round(st["hx_us"], 2), "hx_speedup": round(st["hx_us"] / tb["hx_us"], 2),
+                     "stored_step_us": round(st["step_us"], 2), "tabulated_step_us": round(tb["step_us"], 2),
+                     "step_speedup": round(st["step_us"] / tb["step_us"], 2),
+                     "tabulated_hx_bytes": tb["hx_bytes"], "tabulated_GBs": round(tb["GBs"], 1),
+                     "tabulated_frac_hbm": round(tb["GBs"] / 8000.0, 4),
+                     "max_alpha_diff_vs_stored": float(abs(st["alpha"][:50] - tb["alpha"][:50]).max())}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,9 +272,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c3t"],
                     help="c3: H.x GB/s in Lanczos (default); c2: FP32 vs FP64 eigenvalues; "
-                         "c4: batched multi-vector H.X")
+                         "c4: batched multi-vector H.X; c3t: the c3 alloy with tabulated bond blocks")
     ap.add_argument("--c2-m", type=int, default=6000)
     ap.add_argument("--c2-cand", type=int, default=256)
     a = ap.parse_args()
@@ -249,6 +290,9 @@ def main():
         return
     if a.workload == "c4":
         bench_c4(a)
+        return
+    if a.workload == "c3t":
+        bench_c3t(a)
         return
 
     import torch

@@ -139,6 +139,18 @@ typedef struct {
     /* TBH_F32 only: also keep the atom-major block copy the multi-vector
      * kernels read (tbh_apply_h_multi, tbh_batch_*). */
     int32_t multi_vector;
+    /* 1: store each distinct bond block once, in a table indexed by
+     * (sublattice, species of the atom, species of the neighbour, bond slot),
+     * plus an 8-byte key record per atom, instead of four blocks per atom.
+     * The Slater-Koster blocks of an unstrained real H at Gamma depend on
+     * nothing else (Sec. I: two-centre nearest-neighbour form), so H.x then
+     * reads about 110 instead of 1,700 bytes per atom (sp3d5s*).  Needs: no
+     * bond_scale, Gamma (real H), no spin, no passivation (diagonal on-site
+     * blocks), lanes_per_atom 0, no multi_vector, and a table of at most
+     * 48 KB; the build verifies every atom's blocks against the table and
+     * returns TBH_EINVAL otherwise.  onsite_pot becomes the ham's per-atom
+     * potential (as tbh_ham_set_potential). */
+    int32_t tabulated;
 } tbh_build_opts;
 
 typedef struct {
@@ -152,8 +164,10 @@ typedef struct {
     int32_t has_f64;          /* FP64 copy present */
     int64_t n_dangling;       /* dangling bond slots */
     int64_t stored_bytes;     /* device bytes of the packed H (main precision) */
-    int64_t hx_bytes;         /* algorithmic bytes of one H.x: packed H +
-                                 neighbour table + x once + y once */
+    int64_t hx_bytes;         /* algorithmic bytes of one H.x: packed H (or
+                                 key records + block table) + neighbour
+                                 table + x once + y once (+ potential) */
+    int32_t tabulated;        /* 1 if the bond blocks are tabulated */
 } tbh_ham_info;
 
 /* Pure host step of the build: neighbour table and the assembled FP64

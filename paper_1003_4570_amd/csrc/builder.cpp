@@ -1,5 +1,3 @@
-#include <algorithm>
-#include <array>
 // Host model builder: input validation, neighbour table, Slater-Koster bond
 // blocks in closed form, on-site blocks, and packing into the layout the
 // H.x kernels stream.
@@ -9,8 +7,11 @@
 // two-centre bond blocks follow the closed-form table of Slater & Koster
 // (Phys. Rev. 94, 1498 (1954), Table I) in the direction cosines (l, m, n)
 // of the bond.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <thread>
 
 #include "tbh_internal.h"
@@ -398,6 +399,133 @@ std::vector<int64_t> locality_order(const int32_t* q, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
         if (perm[size_t(i)] != i) return perm;
     return {};
+}
+
+void tabulate(const HostModel& M, const int64_t* perm, std::vector<double>& table, int& nu,
+              std::vector<uint8_t>& keys) {
+    const int no = M.n_o;
+    const int ns = int(M.onsite_par.size() / 4);
+    TBH_REQUIRE(!M.cplx_h && !M.spin, "tabulated blocks need a real H at Gamma without spin");
+    TBH_REQUIRE(M.bond_scale.empty(), "tabulated blocks need unstrained bonds (no bond_scale)");
+    TBH_REQUIRE(!(M.par.passivation_eV != 0.0 && M.n_dangling > 0),
+                "tabulated blocks need diagonal on-site blocks (no passivation)");
+    TBH_REQUIRE(ns >= 1 && ns <= 4, "tabulated blocks support at most 4 species");
+    // key of a bond slot: (sublattice, species of the atom, species of the
+    // neighbour, slot); every atom's blocks are checked against the first
+    // block seen under its key, in parallel with per-thread tables
+    constexpr int NK = 2 * 4 * 4 * 4;
+    const size_t bsz = size_t(no) * no;
+    HostModel M0 = M;
+    M0.pot.clear();   // the potential is applied per atom by the kernel
+    unsigned nt = std::thread::hardware_concurrency();
+    nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
+    if (M.n < 4096) nt = 1;
+    struct Local {
+        std::vector<double> blk, diag;
+        std::vector<char> has, has_d;
+        bool bad = false;
+        std::string why;
+    };
+    std::vector<Local> loc(nt);
+    auto work = [&](unsigned w, int64_t a0, int64_t a1) {
+        Local& L = loc[w];
+        L.blk.assign(NK * bsz, 0.0);
+        L.has.assign(NK, 0);
+        L.diag.assign(size_t(ns) * no, 0.0);
+        L.has_d.assign(ns, 0);
+        std::vector<cplx> D(bsz), B(4 * bsz);
+        for (int64_t i = a0; i < a1 && !L.bad; ++i) {
+            host_atom_blocks(M0, i, D.data(), B.data());
+            const int si = M.species[i];
+            for (int r = 0; r < no; ++r)
+                for (int c = 0; c < no; ++c) {
+                    const double v = D[size_t(r) * no + c].real();
+                    if (r != c) {
+                        if (v != 0.0) {
+                            L.bad = true;
+                            L.why = "an on-site block is not diagonal";
+                        }
+                    } else if (!L.has_d[si]) {
+                        L.diag[size_t(si) * no + r] = v;
+                    } else if (L.diag[size_t(si) * no + r] != v) {
+                        L.bad = true;
+                        L.why = "on-site energies differ between atoms of one species";
+                    }
+                }
+            L.has_d[si] = 1;
+            for (int b = 0; b < 4; ++b) {
+                const int32_t j = M.nbr[size_t(i) * 4 + b];
+                if (j < 0) continue;
+                const int kid = ((M.sub[i] * 4 + si) * 4 + M.species[j]) * 4 + b;
+                double* t = &L.blk[size_t(kid) * bsz];
+                const cplx* src = &B[size_t(b) * bsz];
+                if (!L.has[kid]) {
+                    for (size_t e = 0; e < bsz; ++e) t[e] = src[e].real();
+                    L.has[kid] = 1;
+                } else {
+                    for (size_t e = 0; e < bsz; ++e)
+                        if (t[e] != src[e].real()) {
+                            L.bad = true;
+                            L.why = "bond blocks are not determined by (sublattice, species pair, slot)";
+                            break;
+                        }
+                }
+            }
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        const int64_t per = (M.n + nt - 1) / nt;
+        for (unsigned w = 0; w < nt; ++w) {
+            const int64_t a0 = w * per, a1 = std::min<int64_t>(M.n, a0 + per);
+            th.emplace_back(work, w, a0, std::max(a0, a1));
+        }
+        for (auto& t : th) t.join();
+    }
+    // merge, checking that the threads agree
+    std::vector<double> blk(NK * bsz, 0.0), diag(size_t(ns) * no, 0.0);
+    std::vector<char> has(NK, 0), has_d(ns, 0);
+    for (const Local& L : loc) {
+        if (L.bad) throw Error(TBH_EINVAL, "tabulated blocks: " + L.why);
+        for (int k = 0; k < NK; ++k) {
+            if (!L.has[k]) continue;
+            if (!has[k]) {
+                std::copy(L.blk.begin() + k * bsz, L.blk.begin() + (k + 1) * bsz, blk.begin() + k * bsz);
+                has[k] = 1;
+            } else if (!std::equal(L.blk.begin() + k * bsz, L.blk.begin() + (k + 1) * bsz, blk.begin() + k * bsz)) {
+                throw Error(TBH_EINVAL, "tabulated blocks: bond blocks are not determined by the key");
+            }
+        }
+        for (int sp = 0; sp < ns; ++sp) {
+            if (!L.has_d[sp]) continue;
+            if (!has_d[sp]) {
+                std::copy(L.diag.begin() + sp * no, L.diag.begin() + (sp + 1) * no, diag.begin() + sp * no);
+                has_d[sp] = 1;
+            } else if (!std::equal(L.diag.begin() + sp * no, L.diag.begin() + (sp + 1) * no, diag.begin() + sp * no)) {
+                throw Error(TBH_EINVAL, "tabulated blocks: on-site energies differ within a species");
+            }
+        }
+    }
+    // dense table
+    int dense[NK];
+    nu = 0;
+    for (int k = 0; k < NK; ++k) dense[k] = has[k] ? nu++ : -1;
+    TBH_REQUIRE(nu <= 254, "too many distinct bond blocks");
+    table.assign(size_t(nu) * bsz + size_t(ns) * no, 0.0);
+    for (int k = 0; k < NK; ++k)
+        if (has[k]) std::copy(blk.begin() + k * bsz, blk.begin() + (k + 1) * bsz, table.begin() + dense[k] * bsz);
+    std::copy(diag.begin(), diag.end(), table.begin() + size_t(nu) * bsz);
+    // key records in stream order
+    keys.assign(size_t(M.n) * 8, 0);
+    for (int64_t k = 0; k < M.n; ++k) {
+        const int64_t i = perm ? perm[k] : k;
+        uint8_t* r = &keys[size_t(k) * 8];
+        for (int b = 0; b < 4; ++b) {
+            const int32_t j = M.nbr[size_t(i) * 4 + b];
+            r[b] = j < 0 ? 255 : uint8_t(dense[((M.sub[i] * 4 + M.species[i]) * 4 + M.species[j]) * 4 + b]);
+        }
+        r[4] = M.species[i];
+    }
 }
 
 void pack_atom_major(const HostModel& M, int64_t stride, float* dst) {

@@ -61,6 +61,7 @@ void apply_in_caller_order(tbh::Ham& h, const void* blocks, const tbh::Layout& l
     tbh::HxArgs a;
     a.blocks = blocks;
     a.nbr = h.nbr_d.as<int32_t>();
+    a.keys = h.keys_d.as<uint8_t>();
     a.pot = h.has_pot ? h.pot_d.as<double>() : nullptr;
     a.n_atoms = h.n;
     hipStream_t st = h.ctx->stream;
@@ -178,23 +179,81 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         }
         // diagonal on-site blocks need no spin-orbit, no passivation
         h->diag = !M.spin && !(M.par.passivation_eV != 0.0 && M.n_dangling > 0);
-        const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);
-        h->lay = tbh::make_layout(M.n, M.n_o, M.cplx_h, o->prec, R, h->diag);
-        {
-            std::vector<char> host(size_t(h->lay.bytes));
-            tbh::pack_layout(M, h->lay, h->diag, host.data(), perm);
-            h->blocks.alloc(host.size());
-            TBH_HIP(hipMemcpy(h->blocks.p, host.data(), host.size(), hipMemcpyHostToDevice));
-        }
-        if (o->prec == TBH_F32 && o->keep_f64) {
-            h->lay64 = tbh::make_layout(M.n, M.n_o, M.cplx_h, TBH_F64, R, h->diag);
-            std::vector<char> host(size_t(h->lay64.bytes));
-            tbh::pack_layout(M, h->lay64, h->diag, host.data(), perm);
-            h->blocks64.alloc(host.size());
-            TBH_HIP(hipMemcpy(h->blocks64.p, host.data(), host.size(), hipMemcpyHostToDevice));
-            h->has_f64 = true;
-        } else if (o->prec == TBH_F64) {
-            h->has_f64 = true;
+        if (o->tabulated) {
+            TBH_REQUIRE(!o->multi_vector, "tabulated blocks do not combine with multi_vector");
+            TBH_REQUIRE(o->lanes_per_atom == 0 || o->lanes_per_atom == 1, "tabulated blocks use one lane per atom");
+            TBH_REQUIRE(M.n_o == 5 || M.n_o == 10, "tabulated blocks need 5 or 10 orbitals per atom");
+            std::vector<double> table;
+            std::vector<uint8_t> keys;
+            int nu = 0;
+            tbh::tabulate(M, perm, table, nu, keys);
+            auto tab_layout = [&](int prec) {
+                tbh::Layout L;
+                L.tab = true;
+                L.n_o = M.n_o;
+                L.R = M.n_o;
+                L.G = 1;
+                L.A = 64;
+                L.L = 64;
+                L.cs = 1;
+                L.esz = prec == TBH_F64 ? 8 : 4;
+                L.K = 16 / L.esz;
+                L.diag = true;
+                L.n_tiles = (M.n + 63) / 64;
+                L.nu = nu;
+                L.ns = int(M.onsite_par.size() / 4);
+                L.bytes = int64_t(table.size()) * L.esz + int64_t(keys.size());
+                TBH_REQUIRE(int64_t(table.size()) * L.esz <= 49152, "block table larger than 48 KB");
+                return L;
+            };
+            auto upload = [&](tbh::DevBuf& dst, int prec) {
+                if (prec == TBH_F64) {
+                    dst.alloc(table.size() * 8);
+                    TBH_HIP(hipMemcpy(dst.p, table.data(), table.size() * 8, hipMemcpyHostToDevice));
+                } else {
+                    std::vector<float> t32(table.begin(), table.end());
+                    dst.alloc(t32.size() * 4);
+                    TBH_HIP(hipMemcpy(dst.p, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+                }
+            };
+            h->lay = tab_layout(o->prec);
+            upload(h->blocks, o->prec);
+            h->keys_d.alloc(keys.size());
+            TBH_HIP(hipMemcpy(h->keys_d.p, keys.data(), keys.size(), hipMemcpyHostToDevice));
+            if (o->prec == TBH_F32 && o->keep_f64) {
+                h->lay64 = tab_layout(TBH_F64);
+                upload(h->blocks64, TBH_F64);
+                h->has_f64 = true;
+            } else if (o->prec == TBH_F64) {
+                h->has_f64 = true;
+            }
+            // the input potential becomes the per-atom potential of the kernel
+            if (!M.pot.empty()) {
+                std::vector<double> pot(size_t(M.n));
+                for (int64_t k = 0; k < M.n; ++k) pot[size_t(k)] = M.pot[size_t(perm ? perm[k] : k)];
+                h->pot_d.alloc(pot.size() * 8);
+                TBH_HIP(hipMemcpy(h->pot_d.p, pot.data(), pot.size() * 8, hipMemcpyHostToDevice));
+                h->has_pot = true;
+            }
+        } else {
+            const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);
+            h->lay = tbh::make_layout(M.n, M.n_o, M.cplx_h, o->prec, R, h->diag);
+            {
+                std::vector<char> host(size_t(h->lay.bytes));
+                tbh::pack_layout(M, h->lay, h->diag, host.data(), perm);
+                h->blocks.alloc(host.size());
+                TBH_HIP(hipMemcpy(h->blocks.p, host.data(), host.size(), hipMemcpyHostToDevice));
+            }
+            if (o->prec == TBH_F32 && o->keep_f64) {
+                h->lay64 = tbh::make_layout(M.n, M.n_o, M.cplx_h, TBH_F64, R, h->diag);
+                std::vector<char> host(size_t(h->lay64.bytes));
+                tbh::pack_layout(M, h->lay64, h->diag, host.data(), perm);
+                h->blocks64.alloc(host.size());
+                TBH_HIP(hipMemcpy(h->blocks64.p, host.data(), host.size(), hipMemcpyHostToDevice));
+                h->has_f64 = true;
+            } else if (o->prec == TBH_F64) {
+                h->has_f64 = true;
+            }
         }
         if (o->multi_vector) {
             TBH_REQUIRE(o->prec == TBH_F32, "multi_vector needs TBH_F32");
@@ -248,6 +307,7 @@ int tbh_ham_info_get(const tbh_ham* h, tbh_ham_info* out) {
         out->n_dangling = h->n_dangling;
         out->stored_bytes = h->lay.bytes;
         out->hx_bytes = h->hx_bytes();
+        out->tabulated = h->lay.tab;
     });
 }
 

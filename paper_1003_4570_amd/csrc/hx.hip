@@ -218,6 +218,7 @@ struct HxK {
     double* partial;
     int64_t n_atoms;
     int64_t n_tiles;
+    const uint8_t* keys;   // tabulated layout: key records [n][8]
 };
 
 template <typename T, bool CPLX, int NO, int R, bool DIAG, bool LZ>
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_kernel(HxK a) {
 
 template <typename T, bool CPLX, int NO, int R, bool DIAG>
 void launch_one(const Layout& lay, const HxArgs& h, hipStream_t s) {
-    HxK k;
+    HxK k{};
     k.blocks = h.blocks;
     k.nbr = h.nbr;
     k.x = h.x;
@@ -391,6 +392,112 @@ void launch_shape(const Layout& lay, const HxArgs& h, hipStream_t s) {
     throw Error(TBH_EINVAL, "no H.x kernel for n_o=" + std::to_string(no) + " rows/lane=" + std::to_string(r));
 }
 
+
+// ---------------------------------------------------------------------------
+// Tabulated bond blocks.  In an unstrained real H at Gamma every bond block
+// is fixed by (sublattice, species pair, bond slot): the two-centre
+// Slater-Koster form depends only on the species and the bond direction.  The
+// table of the distinct blocks (12.8 KB for a two-species sp3d5s* alloy in
+// FP32) is staged in LDS once per workgroup; per atom the kernel streams an
+// 8-byte key record, the neighbour indices and the vectors, about 110 bytes
+// instead of 1.7 KB.  One atom per lane, one tile of 64 atoms per wavefront.
+// ---------------------------------------------------------------------------
+template <typename T, int NO, bool LZ>
+__global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int ns) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* tab = reinterpret_cast<T*>(smem);
+    constexpr int ROWB = NO * sizeof(T);
+    constexpr int BB = NO * NO;
+    const int nf = nu * BB + ns * NO;
+    const T* __restrict__ gt = static_cast<const T*>(a.blocks);
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) tab[i] = gt[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t atom = (blk * HX_WPB + wave) * 64 + lane;
+    double pa = 0.0, pw = 0.0;
+    if (atom < a.n_atoms) {
+        const T* __restrict__ x = static_cast<const T*>(a.x);
+        const uint2 kr = reinterpret_cast<const uint2*>(a.keys)[atom];
+        const int4 nb = reinterpret_cast<const int4*>(a.nbr)[atom];
+        const int32_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+        T xo[NO];
+        load_row<T, NO, ROWB>(x + atom * NO, xo);
+        T xv[4][NO];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) load_row<T, NO, ROWB>(x + (nbs[b] >= 0 ? int64_t(nbs[b]) : atom) * NO, xv[b]);
+        const int sp = int(kr.y & 0xffu);
+        const T u = a.pot ? T(a.pot[atom]) : T(0);
+        T acc[NO];
+        const T* __restrict__ dg = tab + nu * BB + sp * NO;
+#pragma unroll
+        for (int r = 0; r < NO; ++r) acc[r] = (dg[r] + u) * xo[r];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const unsigned key = (kr.x >> (8 * b)) & 0xffu;
+            if (key == 255u) continue;   // dangling bond
+            const T* __restrict__ B = tab + key * BB;
+#pragma unroll
+            for (int r = 0; r < NO; ++r)
+#pragma unroll
+                for (int c = 0; c < NO; ++c) acc[r] = fma(B[r * NO + c], xv[b][c], acc[r]);
+        }
+        if constexpr (LZ) {
+            if (a.xprev) {
+                const T bt = T(*a.beta);
+                T xp[NO];
+                load_row<T, NO, ROWB>(static_cast<const T*>(a.xprev) + atom * NO, xp);
+#pragma unroll
+                for (int k = 0; k < NO; ++k) acc[k] = fma(-bt, xp[k], acc[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                pa += double(xo[k]) * double(acc[k]);
+                pw += double(acc[k]) * double(acc[k]);
+            }
+        }
+        store_row<T, NO, ROWB>(static_cast<T*>(a.y) + atom * NO, acc);
+    }
+    if constexpr (LZ) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            pa += __shfl_xor(pa, off, 64);
+            pw += __shfl_xor(pw, off, 64);
+        }
+        if (lane == 0 && a.partial) {
+            const int64_t slot = int64_t(blockIdx.x) * HX_WPB + wave;
+            a.partial[2 * slot] = pa;
+            a.partial[2 * slot + 1] = pw;
+        }
+    }
+}
+
+template <typename T, int NO>
+void launch_tab(const Layout& lay, const HxArgs& h, hipStream_t s) {
+    HxK k{};
+    k.blocks = h.blocks;
+    k.nbr = h.nbr;
+    k.x = h.x;
+    k.y = h.y;
+    k.pot = h.pot;
+    k.xprev = h.xprev;
+    k.beta = h.beta;
+    k.partial = h.partial;
+    k.n_atoms = h.n_atoms;
+    k.n_tiles = lay.n_tiles;
+    k.keys = h.keys;
+    TBH_REQUIRE(h.keys, "tabulated layout without key records");
+    const int64_t nblk = (lay.n_tiles + HX_WPB - 1) / HX_WPB;
+    if (nblk == 0) return;
+    const size_t lds = (size_t(lay.nu) * NO * NO + size_t(lay.ns) * NO) * sizeof(T);
+    TBH_REQUIRE(lds <= 49152, "block table larger than 48 KB");
+    if (h.partial)
+        hipLaunchKernelGGL((hx_tab_kernel<T, NO, true>), dim3(nblk), dim3(64 * HX_WPB), lds, s, k, lay.nu, lay.ns);
+    else
+        hipLaunchKernelGGL((hx_tab_kernel<T, NO, false>), dim3(nblk), dim3(64 * HX_WPB), lds, s, k, lay.nu, lay.ns);
+}
+
 }  // namespace
 
 bool hx_shape_supported(int n_o, bool cplx_h, int R) {
@@ -404,6 +511,18 @@ bool hx_shape_supported(int n_o, bool cplx_h, int R) {
 int64_t hx_num_blocks(const Layout& lay) { return HX_WPB * ((lay.n_tiles + HX_WPB - 1) / HX_WPB); }
 
 void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
+    if (lay.tab) {
+        TBH_REQUIRE(lay.n_o == 5 || lay.n_o == 10, "tabulated blocks need 5 or 10 orbitals");
+        if (f64) {
+            if (lay.n_o == 5) launch_tab<double, 5>(lay, h, s);
+            else launch_tab<double, 10>(lay, h, s);
+        } else {
+            if (lay.n_o == 5) launch_tab<float, 5>(lay, h, s);
+            else launch_tab<float, 10>(lay, h, s);
+        }
+        TBH_HIP(hipGetLastError());
+        return;
+    }
     const bool c = lay.cs == 2;
     if (f64) {
         if (c) launch_shape<double, true>(lay, h, s);

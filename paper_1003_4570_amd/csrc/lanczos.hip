@@ -593,6 +593,7 @@ void enqueue_recurrence(Ham& h, LzWork& W, int m, bool reorth, const double* v0_
         HxArgs a;
         a.blocks = h.blocks.p;
         a.nbr = h.nbr_d.as<int32_t>();
+        a.keys = h.keys_d.as<uint8_t>();
         a.x = vj;
         a.y = W.w.p;
         a.pot = h.has_pot ? h.pot_d.as<double>() : nullptr;
@@ -781,6 +782,7 @@ void ritz_pairs(Ham& h, LzWork& W, int steps, double sigma, int ncand, RitzOut& 
         double* y = out.Y.as<double>() + size_t(c) * ns;
         HxArgs a;
         a.blocks = f64 ? h.blocks.p : h.blocks64.p;
+        a.keys = h.keys_d.as<uint8_t>();
         a.nbr = h.nbr_d.as<int32_t>();
         a.x = y;
         a.y = out.Z.p;

@@ -113,6 +113,10 @@ struct Layout {
     bool diag = false;
     int64_t n_tiles = 0;
     int64_t bytes = 0;
+    // tabulated bond blocks: table of nu blocks [nu][n_o][n_o] followed by
+    // the on-site diagonals [ns][n_o]; 8-byte key record per atom
+    bool tab = false;
+    int nu = 0, ns = 0;
 };
 Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
 // Pack atoms into the layout (T = float or double); slot k of the stream
@@ -123,6 +127,14 @@ void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst, co
 // (stream slot -> caller atom), or an empty vector when the caller's order
 // already is that order.
 std::vector<int64_t> locality_order(const int32_t* pos_q, int64_t n);
+// Tabulated bond blocks (see tbh_build_opts.tabulated): fills table
+// [nu][n_o][n_o] + on-site diagonals [ns][n_o] (FP64) and the key records
+// [n][8] in stream order (perm: stream slot -> caller atom, null = identity):
+// bytes 0..3 the table index of bond slots 0..3 (255 = dangling), byte 4 the
+// atom's species.  The atoms' on-site blocks are taken without M.pot.
+// Throws TBH_EINVAL when the blocks are not determined by the key.
+void tabulate(const HostModel& m, const int64_t* perm, std::vector<double>& table, int& nu,
+              std::vector<uint8_t>& keys);
 // Atom-major FP32 copy for the multi-vector kernels: per atom [5][n_o][n_o]
 // (bond slots 0..3, on-site), complex interleaved, padded to stride floats.
 void pack_atom_major(const HostModel& m, int64_t stride, float* dst);
@@ -141,7 +153,7 @@ struct Ham {
     bool diag = false;
     int64_t n_dangling = 0;
     Layout lay, lay64;
-    DevBuf blocks, blocks64, nbr_d, pot_d, mv_blocks, mv_desc;
+    DevBuf blocks, blocks64, nbr_d, pot_d, mv_blocks, mv_desc, keys_d;
     bool has_f64 = false, has_pot = false, has_mv = false;
     std::vector<int32_t> nbr_h;
     std::vector<int8_t> wrap_h;
@@ -191,6 +203,7 @@ struct HxArgs {
     const void* xprev = nullptr;
     const double* beta = nullptr;    // device scalar (null: 0)
     double* partial = nullptr;       // [n_blocks][2] or null
+    const uint8_t* keys = nullptr;   // tabulated layout: key records [n][8]
 };
 // Number of workgroups a launch of the layout uses (for partial buffers).
 int64_t hx_num_blocks(const Layout& lay);

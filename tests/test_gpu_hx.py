@@ -159,3 +159,70 @@ def test_caller_order_does_not_matter(ctx, prec):
     a1, b1, _ = tbh.lanczos_run(h1, 60, v0.ravel(), reorth=False)
     a2, b2, _ = tbh.lanczos_run(h2, 60, v0[perm].ravel(), reorth=False)
     assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+TAB_CASES = [
+    ("sp3s_periodic", dict(n=2, model=W.MODEL_SP3S)),
+    ("sp3s_ragged_pot", dict(n=3, model=W.MODEL_SP3S, potential=0.3)),
+    ("sp3d5s_alloy", dict(n=3, model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.3)),
+    ("sp3d5s_alloy_pot", dict(n=3, model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.5, potential=0.4)),
+    ("sp3d5s_hardwall", dict(n=2, model=W.MODEL_SP3D5S, periodic=(0, 0, 0))),
+    ("slab_unpassivated", dict(n=0, nxyz=(2, 2, 5), model=W.MODEL_SP3D5S, periodic=(1, 1, 0))),
+]
+
+
+@pytest.mark.parametrize("name,case", TAB_CASES, ids=[c[0] for c in TAB_CASES])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tabulated_hx_parity(ctx, name, case, prec):
+    """Tabulated bond blocks (one table entry per sublattice, species pair
+    and slot, checked against every atom's blocks at build time) against
+    the oracle's CSR H.x; the FP64 copy of an FP32 ham too."""
+    import torch
+    kw = dict(case)
+    n = kw.pop("n")
+    p = W.problem_periodic_cube(n, seed=9, prec=prec, **kw)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, tabulated=True, keep_f64=(prec == "f32")))
+    assert h.info["tabulated"] == 1
+    stored = tbh.build_hamiltonian(ctx, **tbh.problem_args(p))
+    assert h.info["hx_bytes"] < 0.2 * stored.info["hx_bytes"] or p.n_orb == 5
+    rng = np.random.default_rng(1)
+    x, xt = _rand_x(p, rng, False, h.torch_dtype())
+    y = tbh.apply_h(h, xt.cuda())
+    H = T.hamiltonian(p)
+    yr = H @ xt.numpy().astype(np.float64)
+    err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - yr) / np.linalg.norm(yr)
+    assert err <= (1e-12 if prec == "f64" else 1e-5), err
+    if prec == "f32":
+        xd = torch.tensor(x, dtype=torch.float64).cuda()
+        y64 = tbh.apply_h_f64(h, xd).cpu().numpy()
+        assert np.linalg.norm(y64 - H @ x) / np.linalg.norm(H @ x) <= 1e-12
+
+
+@pytest.mark.parametrize("bad", [dict(strain=True), dict(spin=1), dict(kfrac=(0.1, 0.2, 0.0)),
+                                 dict(periodic=(0, 0, 0), passivation=30.0)])
+def test_tabulated_rejects_what_a_table_cannot_hold(ctx, bad):
+    p = W.problem_periodic_cube(2, seed=3, model=W.MODEL_SP3S, **bad)
+    with pytest.raises(tbh.TBHError):
+        tbh.build_hamiltonian(ctx, **tbh.problem_args(p, tabulated=True))
+
+
+def test_tabulated_lanczos_c1(ctx):
+    """C1 eigenvalues through the tabulated format: the same 8 distinct
+    values nearest sigma as dense eigh (FP64, refined to 1e-9 eV), and the
+    Lanczos coefficients equal the stored format's to rounding."""
+    p = W.c1_lanczos_fp64(0)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, tabulated=True))
+    r = tbh.lanczos_eigs(h, p.sigma, p.k, p.m, p.v0, reorth=True)
+    ev = np.linalg.eigvalsh(T.hamiltonian(p).toarray())
+    u = [ev[0]]
+    for e in ev[1:]:
+        if e - u[-1] > 1e-8:
+            u.append(e)
+    u = np.array(u)
+    want = np.sort(u[np.argsort(np.abs(u - p.sigma), kind="stable")[:p.k]])
+    assert r["report"]["n_found"] == p.k
+    assert np.abs(r["refined"] - want).max() < 1e-9
+    hs = tbh.build_hamiltonian(ctx, **tbh.problem_args(p))
+    a1, b1, _ = tbh.lanczos_run(h, 30, p.v0, reorth=False)
+    a2, b2, _ = tbh.lanczos_run(hs, 30, p.v0, reorth=False)
+    assert np.abs(a1 - a2).max() < 1e-10 and np.abs(b1 - b2).max() < 1e-10
