@@ -204,6 +204,7 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
                 L.ns = int(M.onsite_par.size() / 4);
                 L.bytes = int64_t(table.size()) * L.esz + int64_t(keys.size());
                 TBH_REQUIRE(int64_t(table.size()) * L.esz <= 49152, "block table larger than 48 KB");
+                tbh::hx_tab_configure(L);
                 return L;
             };
             auto upload = [&](tbh::DevBuf& dst, int prec) {

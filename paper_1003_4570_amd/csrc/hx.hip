@@ -131,6 +131,7 @@ __device__ __forceinline__ void stream_rows(const typename Vec16<T>::type* __res
 }  // namespace tbh
 
 #include <utility>
+#include <algorithm>
 namespace tbh { namespace {
 template <typename T, bool CPLX, int NO, int R, bool DIAG, int C>
 __device__ __forceinline__ void consume_chunk(const typename Vec16<T>::type& v, const T (&xv)[4][NO * (CPLX ? 2 : 1)],
@@ -413,12 +414,22 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
     for (int i = threadIdx.x; i < nf; i += blockDim.x) tab[i] = gt[i];
     __syncthreads();
 
+    // Each XCD owns a contiguous share of the units of HX_WPB tiles, in
+    // proportion to its blocks, and its blocks sweep that share together
+    // (grid-stride within the XCD): the table is staged once per resident
+    // block while the units in flight on an XCD stay adjacent, so gathered
+    // rows a cell plane back still hit its L2.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t atom = (blk * HX_WPB + wave) * 64 + lane;
+    const int64_t n_units = (a.n_tiles + HX_WPB - 1) / HX_WPB;
+    const int64_t G = gridDim.x, xcd = blockIdx.x % 8, q = G / 8, r = G % 8;
+    const int64_t b_lo = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    const int64_t nb = q + (xcd < r ? 1 : 0);
+    const int64_t u_lo = n_units * b_lo / G, u_hi = n_units * (b_lo + nb) / G;
+    const T* __restrict__ x = static_cast<const T*>(a.x);
     double pa = 0.0, pw = 0.0;
-    if (atom < a.n_atoms) {
-        const T* __restrict__ x = static_cast<const T*>(a.x);
+    for (int64_t u = u_lo + blockIdx.x / 8; u < u_hi; u += nb) {
+        const int64_t atom = (u * HX_WPB + wave) * 64 + lane;
+        if (atom >= a.n_atoms) continue;
         const uint2 kr = reinterpret_cast<const uint2*>(a.keys)[atom];
         const int4 nb = reinterpret_cast<const int4*>(a.nbr)[atom];
         const int32_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
@@ -428,11 +439,11 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
 #pragma unroll
         for (int b = 0; b < 4; ++b) load_row<T, NO, ROWB>(x + (nbs[b] >= 0 ? int64_t(nbs[b]) : atom) * NO, xv[b]);
         const int sp = int(kr.y & 0xffu);
-        const T u = a.pot ? T(a.pot[atom]) : T(0);
+        const T u_at = a.pot ? T(a.pot[atom]) : T(0);
         T acc[NO];
         const T* __restrict__ dg = tab + nu * BB + sp * NO;
 #pragma unroll
-        for (int r = 0; r < NO; ++r) acc[r] = (dg[r] + u) * xo[r];
+        for (int r = 0; r < NO; ++r) acc[r] = (dg[r] + u_at) * xo[r];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const unsigned key = (kr.x >> (8 * b)) & 0xffu;
@@ -473,6 +484,10 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
     }
 }
 
+size_t tab_lds_bytes(const Layout& lay) {
+    return (size_t(lay.nu) * lay.n_o * lay.n_o + size_t(lay.ns) * lay.n_o) * size_t(lay.esz);
+}
+
 template <typename T, int NO>
 void launch_tab(const Layout& lay, const HxArgs& h, hipStream_t s) {
     HxK k{};
@@ -488,14 +503,25 @@ void launch_tab(const Layout& lay, const HxArgs& h, hipStream_t s) {
     k.n_tiles = lay.n_tiles;
     k.keys = h.keys;
     TBH_REQUIRE(h.keys, "tabulated layout without key records");
-    const int64_t nblk = (lay.n_tiles + HX_WPB - 1) / HX_WPB;
-    if (nblk == 0) return;
-    const size_t lds = (size_t(lay.nu) * NO * NO + size_t(lay.ns) * NO) * sizeof(T);
+    if (lay.tab_grid == 0) return;
+    TBH_REQUIRE(lay.tab_grid <= INT32_MAX, "tabulated launch too large");
+    const size_t lds = tab_lds_bytes(lay);
     TBH_REQUIRE(lds <= 49152, "block table larger than 48 KB");
+    const dim3 g(unsigned(lay.tab_grid)), blk(64 * HX_WPB);
     if (h.partial)
-        hipLaunchKernelGGL((hx_tab_kernel<T, NO, true>), dim3(nblk), dim3(64 * HX_WPB), lds, s, k, lay.nu, lay.ns);
+        hipLaunchKernelGGL((hx_tab_kernel<T, NO, true>), g, blk, lds, s, k, lay.nu, lay.ns);
     else
-        hipLaunchKernelGGL((hx_tab_kernel<T, NO, false>), dim3(nblk), dim3(64 * HX_WPB), lds, s, k, lay.nu, lay.ns);
+        hipLaunchKernelGGL((hx_tab_kernel<T, NO, false>), g, blk, lds, s, k, lay.nu, lay.ns);
+}
+
+// resident blocks of the fused (Lanczos) instance on the current device
+template <typename T, int NO>
+int tab_resident(size_t lds) {
+    int dev = 0, cus = 0, occ = 0;
+    TBH_HIP(hipGetDevice(&dev));
+    TBH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    TBH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hx_tab_kernel<T, NO, true>, 64 * HX_WPB, lds));
+    return std::max(1, cus * std::max(1, occ));
 }
 
 }  // namespace
@@ -508,7 +534,20 @@ bool hx_shape_supported(int n_o, bool cplx_h, int R) {
 }
 
 // partial-sum slots a fused Lanczos launch writes (one per wavefront)
-int64_t hx_num_blocks(const Layout& lay) { return HX_WPB * ((lay.n_tiles + HX_WPB - 1) / HX_WPB); }
+int64_t hx_num_blocks(const Layout& lay) {
+    if (lay.tab) return HX_WPB * lay.tab_grid;
+    return HX_WPB * ((lay.n_tiles + HX_WPB - 1) / HX_WPB);
+}
+
+void hx_tab_configure(Layout& lay) {
+    TBH_REQUIRE(lay.tab && (lay.n_o == 5 || lay.n_o == 10), "tabulated blocks need 5 or 10 orbitals");
+    const size_t lds = tab_lds_bytes(lay);
+    int res;
+    if (lay.esz == 8) res = lay.n_o == 5 ? tab_resident<double, 5>(lds) : tab_resident<double, 10>(lds);
+    else res = lay.n_o == 5 ? tab_resident<float, 5>(lds) : tab_resident<float, 10>(lds);
+    const int64_t n_units = (lay.n_tiles + HX_WPB - 1) / HX_WPB;
+    lay.tab_grid = std::min<int64_t>(n_units, res);
+}
 
 void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
     if (lay.tab) {

@@ -117,6 +117,9 @@ struct Layout {
     // the on-site diagonals [ns][n_o]; 8-byte key record per atom
     bool tab = false;
     int nu = 0, ns = 0;
+    // blocks of the tabulated launch (at most those resident on the device;
+    // hx_tab_configure)
+    int64_t tab_grid = 0;
 };
 Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
 // Pack atoms into the layout (T = float or double); slot k of the stream
@@ -205,8 +208,10 @@ struct HxArgs {
     double* partial = nullptr;       // [n_blocks][2] or null
     const uint8_t* keys = nullptr;   // tabulated layout: key records [n][8]
 };
-// Number of workgroups a launch of the layout uses (for partial buffers).
+// Partial-sum slots a fused launch of the layout writes (one per wavefront).
 int64_t hx_num_blocks(const Layout& lay);
+// Sizes the tabulated launch to the blocks resident on the current device.
+void hx_tab_configure(Layout& lay);
 bool hx_shape_supported(int n_o, bool cplx_h, int R);
 void hx_launch(const Layout& lay, bool f64, const HxArgs& a, hipStream_t s);
 
