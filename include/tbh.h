@@ -181,6 +181,25 @@ int tbh_build_blocks_host(const tbh_geometry* g, const tbh_params* p,
                           const tbh_build_opts* o, int32_t* nbr, int8_t* wrap,
                           double* onsite, double* bonds, int32_t* is_complex);
 
+/* Pure host step of the tabulated build (tbh_build_opts.tabulated): the
+ * distinct bond blocks and per-species on-site diagonals of an unstrained
+ * real H at Gamma without spin or passivation (the two-centre blocks of
+ * Sec. I depend only on the species pair and the bond direction), and each
+ * atom's key record, in the caller's atom order.  No device is touched.
+ * table: host, table_cap doubles; on success it holds the nu blocks
+ *   [nu][n_o][n_o] (block of bond (i,b) = <i,row|H|nbr(i,b),col>) followed
+ *   by the on-site diagonals [n_species][n_o] without the potential; NULL
+ *   writes only *n_blocks, so a caller can size the table first
+ *   (nu * n_o * n_o + n_species * n_o doubles).
+ * keys: host [n_atoms][8] bytes or NULL: bytes 0..3 the table index of
+ *   bond slot b (255 = dangling), byte 4 the atom's species, bytes 5..7 zero.
+ * n_blocks: out, nu.
+ * TBH_EINVAL when the model cannot be tabulated (strain, spin, k-point,
+ * passivated dangling bonds, more than 4 species) or table_cap is short. */
+int tbh_tabulate_host(const tbh_geometry* g, const tbh_params* p,
+                      const tbh_build_opts* o, double* table, int64_t table_cap,
+                      int32_t* n_blocks, uint8_t* keys);
+
 /* Build H on the context's device: neighbour search, Slater-Koster bond
  * blocks (strain, Bloch phase), on-site blocks (spin-orbit, passivation,
  * potential), packed into the atom-ordered block layout the kernels stream.

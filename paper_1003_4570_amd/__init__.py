@@ -101,6 +101,9 @@ _SIGS = [
     ("tbh_build_blocks_host", C.c_int, [C.POINTER(tbh_geometry), C.POINTER(tbh_params),
                                         C.POINTER(tbh_build_opts), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    ("tbh_tabulate_host", C.c_int, [C.POINTER(tbh_geometry), C.POINTER(tbh_params),
+                                    C.POINTER(tbh_build_opts), C.c_void_p, C.c_int64,
+                                    C.POINTER(C.c_int32), C.c_void_p]),
     ("tbh_build_hamiltonian", C.c_int, [C.c_void_p, C.POINTER(tbh_geometry), C.POINTER(tbh_params),
                                         C.POINTER(tbh_build_opts), C.POINTER(C.c_void_p)]),
     ("tbh_ham_destroy", C.c_int, [C.c_void_p]),
@@ -250,6 +253,22 @@ def build_blocks_host(**kw):
         on = on.view(np.complex128)
         bd = bd.view(np.complex128)
     return nbr, wrap, on.reshape(n, no, no), bd.reshape(n, 4, no, no), bool(isc.value)
+
+
+def tabulate_host(**kw):
+    """Host-only tabulated build step: (blocks [nu, n_o, n_o], on-site
+    diagonals [n_species, n_o], key records [n, 8] uint8) in caller order."""
+    a = _Inputs(**kw)
+    nu = C.c_int32(0)
+    _check(lib().tbh_tabulate_host(C.byref(a.g), C.byref(a.par), C.byref(a.opt), None, 0,
+                                   C.byref(nu), None))
+    no, ns = a.n_o, int(a.par.n_species)
+    table = np.empty(nu.value * no * no + ns * no)
+    keys = np.empty((a.n, 8), np.uint8)
+    _check(lib().tbh_tabulate_host(C.byref(a.g), C.byref(a.par), C.byref(a.opt), table.ctypes.data,
+                                   table.size, C.byref(nu), keys.ctypes.data))
+    k = nu.value * no * no
+    return table[:k].reshape(nu.value, no, no), table[k:].reshape(ns, no), keys
 
 
 class Context:

@@ -148,6 +148,25 @@ int tbh_build_blocks_host(const tbh_geometry* g, const tbh_params* p, const tbh_
     });
 }
 
+int tbh_tabulate_host(const tbh_geometry* g, const tbh_params* p, const tbh_build_opts* o, double* table,
+                      int64_t table_cap, int32_t* n_blocks, uint8_t* keys) {
+    return guard([&] {
+        TBH_REQUIRE(n_blocks, "null output pointer");
+        tbh::HostModel M;
+        tbh::host_prepare(g, p, o, M);
+        std::vector<double> t;
+        std::vector<uint8_t> k;
+        int nu = 0;
+        tbh::tabulate(M, nullptr, t, nu, k);
+        *n_blocks = nu;
+        if (table) {
+            TBH_REQUIRE(table_cap >= int64_t(t.size()), "table capacity too small");
+            std::memcpy(table, t.data(), t.size() * sizeof(double));
+        }
+        if (keys) std::memcpy(keys, k.data(), k.size());
+    });
+}
+
 int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params* p,
                           const tbh_build_opts* o, tbh_ham** out) {
     return guard([&] {

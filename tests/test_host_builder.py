@@ -177,3 +177,51 @@ def test_point_ops_are_symmetries_of_the_study_slab():
         assert torch.equal(op(m), m)
         assert torch.equal(op(sites), sites)
         assert torch.equal(inv(op(a)), a)
+
+
+TAB_HOST_CASES = [
+    dict(n=2, model=W.MODEL_SP3S),
+    dict(n=3, model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.3, potential=0.4),
+    dict(n=2, model=W.MODEL_SP3D5S, periodic=(0, 0, 0)),
+    dict(n=0, nxyz=(2, 2, 5), model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.5, periodic=(1, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("case", TAB_HOST_CASES)
+def test_tabulated_table_and_keys_match_oracle_blocks(case):
+    """The table of distinct bond blocks and the per-atom key records against
+    the oracle's blocks, built bond by bond from each bond's own direction:
+    every bond's looked-up block equals its block, dangling slots are marked,
+    the key is a function of (sublattice, species pair, slot), every entry is
+    used, and the on-site diagonals equal the on-site blocks less the
+    potential."""
+    c = dict(case)
+    n = c.pop("n")
+    p = W.problem_periodic_cube(n, seed=7, **c)
+    blocks, diag, keys = tbh.tabulate_host(**tbh.problem_args(p, tabulated=True))
+    blk = T.build_blocks(p)
+    nbr, no, N = blk["nbr"], blk["n_o"], p.n_atoms
+    spc = np.asarray(p.species, dtype=np.int64)
+    assert np.array_equal(keys[:, :4] == 255, nbr < 0)
+    assert np.array_equal(keys[:, 4], spc)
+    assert not keys[:, 5:].any()
+    i, b = np.nonzero(nbr >= 0)
+    k = keys[i, b].astype(np.int64)
+    assert np.array_equal(np.unique(k), np.arange(blocks.shape[0]))
+    assert np.abs(blocks[k] - blk["bonds"][i, b]).max() < 1e-13
+    sub = T.sublattice(p.pos_q)
+    cls = ((sub[i] * 4 + spc[i]) * 4 + spc[nbr[i, b]]) * 4 + b
+    for c_ in np.unique(cls):
+        assert np.unique(k[cls == c_]).size == 1
+    U = np.zeros(N) if p.onsite_pot is None else np.asarray(p.onsite_pot, dtype=np.float64)
+    D = np.zeros((N, no, no))
+    D[:, np.arange(no), np.arange(no)] = diag[spc]
+    assert np.abs(blk["onsite"] - U[:, None, None] * np.eye(no) - D).max() < 1e-13
+
+
+@pytest.mark.parametrize("bad", [dict(strain=True), dict(spin=1), dict(kfrac=(0.1, 0.2, 0.0)),
+                                 dict(periodic=(0, 0, 0), passivation=30.0)])
+def test_tabulate_refuses_what_a_table_cannot_hold(bad):
+    p = W.problem_periodic_cube(2, seed=3, model=W.MODEL_SP3S, **bad)
+    with pytest.raises(tbh.TBHError):
+        tbh.tabulate_host(**tbh.problem_args(p, tabulated=True))
