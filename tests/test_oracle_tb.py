@@ -218,3 +218,24 @@ def test_gap_table_entries_reproduce():
         assert c - v >= 0.5
         assert abs(e["vbm"] - v) < 1e-12 and abs(e["cbm"] - c) < 1e-12
         assert abs(e["mid"] - 0.5 * (e["vbm"] + e["cbm"])) < 1e-12
+
+
+def test_paper_structure_size_44nm_silicon_cube():
+    """The silicon cube of the 3-D decomposition test (80 unit cells per
+    direction, 44 nm edge, about 4 million atoms) as the lattice generator
+    and the oracle's sublattice rule produce it: 8 distinct atoms per
+    conventional cell, half on each sublattice, 80 planes of cells along
+    any axis (the 1-D decomposition limit), and an edge of 80 a."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "structure_sizes.json")))
+    n = g["cells_per_axis"]
+    pos = W.diamond_positions(n, n, n)
+    assert pos.shape == (8 * n ** 3, 3)
+    assert abs(pos.shape[0] - g["atoms_approx"]) <= g["atoms_rel_tol"] * g["atoms_approx"]
+    key = (pos[:, 0].astype(np.int64) * (4 * n) + pos[:, 1]) * (4 * n) + pos[:, 2]
+    assert np.unique(key).size == pos.shape[0]
+    sub = T.sublattice(pos)
+    assert int(sub.sum()) == pos.shape[0] // 2
+    assert np.unique(pos[:, 2] // 4).size == g["max_1d_slabs"]
+    assert abs(n * g["si_lattice_constant_nm"] - g["edge_nm"]) <= 0.02 * g["edge_nm"]
