@@ -92,10 +92,31 @@ def electron_density(E, wts, Ua, sigma_mid, n_elec, kT, Ef=None):
     return n, Ef, cb
 
 
+def loop_body(H0, n_o, nodes, nd, U, grid, sigma_mid, n_elec, kT, h, eps_r, Ef_fixed, cg_tol):
+    """One pass of the loop body at input potential U [nz, ny, nx] (eV):
+    eigenstates of H(U) = H_TB + U at every orbital of each atom, electrons
+    per atom from the CB-like states, rho = e (N_D - n) / h^3 at the atom
+    nodes, and U_out = -phi from the Poisson equation (CG started from -U).
+    Returns dict(U_out, rho, Ef, n)."""
+    nx, ny, nz = grid
+    Ua = U.ravel()[nodes]
+    Hm = H0 + np.diag(np.repeat(Ua, n_o))
+    E, psi = np.linalg.eigh(Hm)
+    wts = atom_weights(psi, n_o)
+    n_i, Ef, _ = electron_density(E, wts, Ua, sigma_mid, n_elec, kT, Ef_fixed)
+    rho = nd.copy()
+    np.add.at(rho, nodes, -n_i)
+    rho = (rho / h ** 3).reshape(nz, ny, nx)
+    Uout, _, _ = P.potential_energy(rho, h, eps_r, U0=U, rel_tol=cg_tol)
+    return dict(U_out=Uout, rho=rho, Ef=Ef, n=n_i)
+
+
 def scf(prob, donors, grid, U0, sigma_mid, alpha=0.1, tol=1e-4, max_iter=200, T_K=4.0,
         eps_r=11.7, h_nm=None, Ef_fixed=None, cg_tol=1e-12, keep_iterates=True):
     """Self-consistent loop with dense eigenstates.  U0: [nz, ny, nx] (eV).
-    Returns dict(U, iterations, residuals, iterates, Ef, converged)."""
+    Returns dict(U, iterations, residuals, iterates, rhos, outputs, Ef,
+    converged): iterates[t] is the input potential of step t, rhos[t] and
+    outputs[t] its charge density and U_out (kept with keep_iterates)."""
     from workloads import H_GRID_NM
     h = H_GRID_NM if h_nm is None else h_nm
     nx, ny, nz = grid
@@ -108,26 +129,21 @@ def scf(prob, donors, grid, U0, sigma_mid, alpha=0.1, tol=1e-4, max_iter=200, T_
     np.add.at(nd, nodes[donors], 1.0)
     n_elec = float(len(donors))
     U = np.array(U0, dtype=np.float64).reshape(nz, ny, nx).copy()
-    res_hist, iterates, efs = [], [], []
+    res_hist, iterates, rhos, outs, efs = [], [], [], [], []
     converged = False
     for it in range(max_iter):
-        Ua = U.ravel()[nodes]
-        Hm = H0 + np.diag(np.repeat(Ua, n_o))
-        E, psi = np.linalg.eigh(Hm)
-        wts = atom_weights(psi, n_o)
-        n_i, Ef, _ = electron_density(E, wts, Ua, sigma_mid, n_elec, kT, Ef_fixed)
-        rho = nd.copy()
-        np.add.at(rho, nodes, -n_i)
-        rho = (rho / h ** 3).reshape(nz, ny, nx)
-        Uout, _, _ = P.potential_energy(rho, h, eps_r, U0=U, rel_tol=cg_tol)
+        o = loop_body(H0, n_o, nodes, nd, U, grid, sigma_mid, n_elec, kT, h, eps_r, Ef_fixed, cg_tol)
+        Uout = o["U_out"]
         res = float(np.abs(Uout - U).max())
         res_hist.append(res)
-        efs.append(Ef)
+        efs.append(o["Ef"])
         if keep_iterates:
             iterates.append(U.copy())
+            rhos.append(o["rho"])
+            outs.append(Uout)
         if res < tol:
             converged = True
             break
         U = U + alpha * (Uout - U)
-    return dict(U=U, iterations=len(res_hist), residuals=res_hist, iterates=iterates, Ef=efs,
-                converged=converged)
+    return dict(U=U, iterations=len(res_hist), residuals=res_hist, iterates=iterates, rhos=rhos,
+                outputs=outs, Ef=efs, converged=converged)
