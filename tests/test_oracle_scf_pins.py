@@ -146,18 +146,22 @@ def test_donor_plane_is_the_potential_minimum_after_one_step():
     assert abs(zc - zp) < abs(zc - zm), (zc, zp, zm)
 
 
-def test_one_occupied_state_charge_density():
+@pytest.mark.parametrize("shift", [0.0, -1.5])
+def test_one_occupied_state_charge_density(shift):
     """Fixed Fermi level between the two lowest conduction-band-like states at
     T = 0: exactly one state holds two electrons, so rho at the node of atom i
     is e (N_D(i) - 2 sum_alpha |psi_1(i, alpha)|^2) / h^3 and zero on empty
     nodes.  The eigenpair comes from a dense solve of H(U) built with U on the
-    per-atom on-site blocks; node (x, y, z) has index (z ny + y) nx + x."""
+    per-atom on-site blocks; node (x, y, z) has index (z ny + y) nx + x.
+    A uniform shift of U by more than half the gap moves the conduction band
+    below the gap centre; a state is still conduction-band-like by its energy
+    less its mean potential, so the same state is the one filled."""
     p = _slab(nz=3, nxy=1, n_donors=1, seed=2)
     grid = p.extra["grid"]
     nx, ny, nz = grid
     gap = p.extra["gap"]
     rng = np.random.default_rng(9)
-    U0 = rng.uniform(-0.05, 0.05, size=(nz, ny, nx))       # breaks every degeneracy
+    U0 = shift + rng.uniform(-0.05, 0.05, size=(nz, ny, nx))       # breaks every degeneracy
     q = p.pos_q
     Ua = U0[q[:, 2], q[:, 1], q[:, 0]]
     pu = W.problem_periodic_cube(0, seed=0, model=W.MODEL_SP3D5S, spin=0, periodic=(1, 1, 0),
@@ -169,6 +173,8 @@ def test_one_occupied_state_charge_density():
     w = (psi ** 2).T.reshape(len(E), -1, n_o).sum(axis=2)
     cb = np.flatnonzero(E - w @ Ua > gap["mid"])
     e1, e2 = E[cb[0]], E[cb[1]]
+    if shift:
+        assert e1 < gap["mid"]        # below the gap centre, counted only through E - <U>
     assert e2 - e1 > 1e-6
     ef = 0.5 * (e1 + e2)
     r = S.scf(p, p.extra["donor_atoms"], grid, U0, gap["mid"], alpha=0.1, tol=0.0, max_iter=1, T_K=0.0,
