@@ -123,7 +123,9 @@ typedef struct {
      * bond uses its A atom's factor. */
     const double* bond_scale;
     /* host [n_atoms] on-site potential energy (eV) added to every orbital of
-     * the atom, or NULL = 0. */
+     * the atom, or NULL = 0.  It becomes the ham's per-atom potential (in
+     * every storage format it is kept beside the packed blocks, not inside
+     * them), so a later tbh_ham_set_potential replaces it. */
     const double* onsite_pot;
     /* host [3] Bloch vector as fractions of the box reciprocal vectors; a
      * bond that wraps by w boxes gets the phase exp(2 pi i k.w).  NULL =
@@ -212,8 +214,10 @@ int tbh_ham_info_get(const tbh_ham* h, tbh_ham_info* out);
 int tbh_ham_neighbours(const tbh_ham* h, int32_t* nbr, int8_t* wrap);
 
 /* Replace the per-atom on-site potential (Schrodinger-Poisson update, Sec.
- * III-A item 3): pot_dev is device [n_atoms] FP64 (eV), or NULL = 0.  The
- * blocks are not rebuilt; H.x adds pot[i] * x_i. */
+ * III-A item 3): pot_dev is device [n_atoms] FP64 (eV, caller's atom order),
+ * or NULL = 0.  It replaces the build-time onsite_pot as well, the same way
+ * in every storage format (stored, tabulated, FP64 copy, multi-vector copy).
+ * The blocks are not rebuilt; H.x adds pot[i] * x_i. */
 int tbh_ham_set_potential(tbh_ham* h, const double* pot_dev);
 
 /* y = H x.  x, y: device, [dim] scalars of the ham's precision (complex

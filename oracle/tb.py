@@ -390,10 +390,13 @@ def bulk_hk(model, spin, E, V, so_delta, k_cart):
     return H
 
 
-def hx_rows(prob, atoms, x, nbr=None, wrap=None):
+def hx_rows(prob, atoms, x, nbr=None, wrap=None, absolute=False):
     """Rows of y = H x belonging to the given atoms, computed atom by atom
     from the definition (for spot checks at sizes where the full CSR matrix
-    is too large).  Returns [len(atoms), n_o] (complex if H is complex)."""
+    is too large).  Returns [len(atoms), n_o] (complex if H is complex).
+    With absolute=True every block is replaced by its element-wise absolute
+    value, giving (|H| x)_i: with x = |x| the scale of a row's rounding
+    error bound."""
     par = prob.params
     model, spin = par["model"], par["spin"]
     nb = n_base_orbitals(model)
@@ -412,6 +415,8 @@ def hx_rows(prob, atoms, x, nbr=None, wrap=None):
         U = 0.0 if prob.onsite_pot is None else prob.onsite_pot[i]
         D = onsite_block(model, spin, par["onsite"][spc[i]], U, par["so_delta"][spc[i]],
                          dirs, par["passivation_eV"])
+        if absolute:
+            D = np.abs(D)
         acc = D @ X[i]
         for b in range(4):
             j = nbr[i, b]
@@ -424,6 +429,8 @@ def hx_rows(prob, atoms, x, nbr=None, wrap=None):
                 B = np.kron(np.eye(2), B)
             if cplx:
                 B = B * np.exp(2j * np.pi * np.dot(kf, wrap[i, b]))
+            if absolute:
+                B = np.abs(B)
             acc = acc + B @ X[j]
         out[r] = acc
     return out

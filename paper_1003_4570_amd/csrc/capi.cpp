@@ -198,6 +198,11 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         }
         // diagonal on-site blocks need no spin-orbit, no passivation
         h->diag = !M.spin && !(M.par.passivation_eV != 0.0 && M.n_dangling > 0);
+        // The build-time potential is the ham's per-atom potential in every
+        // storage format: it stays out of the packed blocks and the kernels
+        // add pot[i] x_i, so tbh_ham_set_potential replaces it (NULL = 0).
+        std::vector<double> pot0;
+        pot0.swap(M.pot);
         if (o->tabulated) {
             TBH_REQUIRE(!o->multi_vector, "tabulated blocks do not combine with multi_vector");
             TBH_REQUIRE(o->lanes_per_atom == 0 || o->lanes_per_atom == 1, "tabulated blocks use one lane per atom");
@@ -247,14 +252,6 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
             } else if (o->prec == TBH_F64) {
                 h->has_f64 = true;
             }
-            // the input potential becomes the per-atom potential of the kernel
-            if (!M.pot.empty()) {
-                std::vector<double> pot(size_t(M.n));
-                for (int64_t k = 0; k < M.n; ++k) pot[size_t(k)] = M.pot[size_t(perm ? perm[k] : k)];
-                h->pot_d.alloc(pot.size() * 8);
-                TBH_HIP(hipMemcpy(h->pot_d.p, pot.data(), pot.size() * 8, hipMemcpyHostToDevice));
-                h->has_pot = true;
-            }
         } else {
             const int R = tbh::choose_rows(M.n_o, M.cplx_h, o->prec, M.n, o->lanes_per_atom);
             h->lay = tbh::make_layout(M.n, M.n_o, M.cplx_h, o->prec, R, h->diag);
@@ -283,6 +280,13 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
             h->mv_blocks.alloc(host.size() * 4);
             TBH_HIP(hipMemcpy(h->mv_blocks.p, host.data(), host.size() * 4, hipMemcpyHostToDevice));
             h->has_mv = true;
+        }
+        if (!pot0.empty()) {
+            std::vector<double> pot(size_t(M.n));
+            for (int64_t k = 0; k < M.n; ++k) pot[size_t(k)] = pot0[size_t(perm ? perm[k] : k)];
+            h->pot_d.alloc(pot.size() * 8);
+            TBH_HIP(hipMemcpy(h->pot_d.p, pot.data(), pot.size() * 8, hipMemcpyHostToDevice));
+            h->has_pot = true;
         }
         h->nbr_d.alloc(M.nbr.size() * 4);
         if (h->permuted) {

@@ -421,18 +421,18 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
     // rows a cell plane back still hit its L2.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t n_units = (a.n_tiles + HX_WPB - 1) / HX_WPB;
-    const int64_t G = gridDim.x, xcd = blockIdx.x % 8, q = G / 8, r = G % 8;
-    const int64_t b_lo = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
-    const int64_t nb = q + (xcd < r ? 1 : 0);
-    const int64_t u_lo = n_units * b_lo / G, u_hi = n_units * (b_lo + nb) / G;
+    const int64_t G = gridDim.x, xcd = blockIdx.x % 8, q = G / 8, rem = G % 8;
+    const int64_t b_lo = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+    const int64_t xcd_blocks = q + (xcd < rem ? 1 : 0);   // blocks of this XCD
+    const int64_t u_lo = n_units * b_lo / G, u_hi = n_units * (b_lo + xcd_blocks) / G;
     const T* __restrict__ x = static_cast<const T*>(a.x);
     double pa = 0.0, pw = 0.0;
-    for (int64_t u = u_lo + blockIdx.x / 8; u < u_hi; u += nb) {
+    for (int64_t u = u_lo + blockIdx.x / 8; u < u_hi; u += xcd_blocks) {
         const int64_t atom = (u * HX_WPB + wave) * 64 + lane;
         if (atom >= a.n_atoms) continue;
         const uint2 kr = reinterpret_cast<const uint2*>(a.keys)[atom];
-        const int4 nb = reinterpret_cast<const int4*>(a.nbr)[atom];
-        const int32_t nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+        const int4 nb4 = reinterpret_cast<const int4*>(a.nbr)[atom];
+        const int32_t nbs[4] = {nb4.x, nb4.y, nb4.z, nb4.w};
         T xo[NO];
         load_row<T, NO, ROWB>(x + atom * NO, xo);
         T xv[4][NO];

@@ -43,7 +43,25 @@ def _run(ctx, p, prec, lanes=0, seed=0):
     xr = xt.numpy().astype(np.complex128 if h.is_complex else np.float64)
     yr = H @ xr
     yg = y.cpu().numpy().astype(np.complex128 if h.is_complex else np.float64)
+    row_bound_check(H, xr, yg, yr, prec)
     return np.linalg.norm(yg - yr) / np.linalg.norm(yr), h
+
+
+def row_bound_check(H, x, y, yr, prec):
+    """Per-row forward error bound of a dot product: |y_i - y_ref,i| <=
+    (K + 1) u (|H| |x|)_i with K the terms of row i (K-term summation) plus
+    one rounding of each stored element, u the unit roundoff (2^-24 FP32,
+    2^-53 FP64).  A single wrong row fails it even when the normwise error
+    stays small."""
+    import scipy.sparse as sp
+    A = abs(sp.csr_matrix(H))
+    K = np.diff(A.indptr)
+    u = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    # complex rows: a complex product is 4 real products and 2 sums
+    c = 2.0 if np.iscomplexobj(H) else 1.0
+    bound = c * (K + 1) * u * (A @ np.abs(x)) + 1e-300
+    ratio = np.abs(y - yr) / bound
+    assert ratio.max() <= 1.0, (prec, float(ratio.max()), int(np.argmax(ratio)))
 
 
 CASES = [
@@ -102,6 +120,53 @@ def test_hx_potential_update(ctx):
     assert np.linalg.norm(y0 - T.hamiltonian(p) @ x) / np.linalg.norm(y0) < 1e-12
 
 
+FORMATS = [("stored_f64", dict(prec="f64")), ("stored_f32", dict(prec="f32", keep_f64=True)),
+           ("tabulated_f64", dict(prec="f64", tabulated=True)),
+           ("tabulated_f32", dict(prec="f32", tabulated=True, keep_f64=True)),
+           ("multi_vector", dict(prec="f32", multi_vector=True))]
+
+
+@pytest.mark.parametrize("name,kw", FORMATS, ids=[f[0] for f in FORMATS])
+def test_set_potential_same_rule_every_format(ctx, name, kw):
+    """The build-time potential is the ham's per-atom potential in every
+    storage format: H = H_TB + U_build after the build, H_TB + U after
+    tbh_ham_set_potential(U), H_TB after set_potential(NULL); checked through
+    the main copy, the FP64 copy and the multi-vector copy."""
+    import torch
+    p = W.problem_periodic_cube(3, seed=7, model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.4,
+                                potential=0.5)
+    u_build = p.onsite_pot.copy()
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, **kw))
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, p.dim)
+    f32 = kw["prec"] == "f32"
+    tol = 1e-5 if f32 else 1e-12
+    xq = x.astype(np.float32).astype(np.float64) if f32 else x
+
+    def check(pot):
+        q = W.problem_periodic_cube(3, seed=7, model=W.MODEL_SP3D5S, n_species=2, alloy_frac=0.4)
+        q.onsite_pot = pot
+        H = T.hamiltonian(q)
+        if kw.get("multi_vector"):
+            X = np.repeat(xq[:, None], 16, axis=1)
+            Y = tbh.apply_h_multi(h, torch.tensor(X, dtype=torch.float32).cuda()).cpu().numpy()
+            y = Y[:, 5].astype(np.float64)
+        else:
+            y = tbh.apply_h(h, torch.tensor(xq, dtype=h.torch_dtype()).cuda()).cpu().numpy().astype(np.float64)
+        yr = H @ xq
+        assert np.linalg.norm(y - yr) / np.linalg.norm(yr) <= tol, (name, "main")
+        if kw.get("keep_f64"):
+            y64 = tbh.apply_h_f64(h, torch.tensor(x).cuda()).cpu().numpy()
+            assert np.linalg.norm(y64 - H @ x) / np.linalg.norm(H @ x) <= 1e-12, (name, "f64 copy")
+
+    check(u_build)
+    U = rng.uniform(-0.3, 0.3, p.n_atoms)
+    tbh.ham_set_potential(h, torch.tensor(U).cuda())
+    check(U)
+    tbh.ham_set_potential(h, None)
+    check(None)
+
+
 def test_hx_f64_copy_of_f32_ham(ctx):
     import torch
     p = W.problem_periodic_cube(2, seed=9, model=W.MODEL_SP3D5S, spin=1, periodic=(0, 0, 0),
@@ -135,6 +200,9 @@ def test_hx_c3_full_size_sampled(ctx, tab):
     ref = T.hx_rows(p, atoms, x.numpy().astype(np.float64), nbr=nbr, wrap=wrap)
     got = y.reshape(p.n_atoms, -1)[atoms]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+    # per row: (K + 1) u (|H||x|)_i with K = 41 terms (diagonal on-site + 4 blocks of 10)
+    absref = T.hx_rows(p, atoms, np.abs(x.numpy().astype(np.float64)), nbr=nbr, wrap=wrap, absolute=True)
+    assert (np.abs(got - ref) <= 42 * 2.0 ** -24 * absref + 1e-300).all()
     if tab:
         v0 = np.random.default_rng(5).uniform(-1, 1, h.dim)
         a1, b1, _ = tbh.lanczos_run(h, 8, v0, reorth=False)

@@ -146,14 +146,14 @@ def test_donor_plane_is_the_potential_minimum_after_one_step():
     assert abs(zc - zp) < abs(zc - zm), (zc, zp, zm)
 
 
-@pytest.mark.parametrize("shift", [0.0, -1.5])
+@pytest.mark.parametrize("shift", [0.0, -3.0])
 def test_one_occupied_state_charge_density(shift):
     """Fixed Fermi level between the two lowest conduction-band-like states at
     T = 0: exactly one state holds two electrons, so rho at the node of atom i
     is e (N_D(i) - 2 sum_alpha |psi_1(i, alpha)|^2) / h^3 and zero on empty
     nodes.  The eigenpair comes from a dense solve of H(U) built with U on the
     per-atom on-site blocks; node (x, y, z) has index (z ny + y) nx + x.
-    A uniform shift of U by more than half the gap moves the conduction band
+    A uniform shift of U by 3 eV moves this small slab's conduction band
     below the gap centre; a state is still conduction-band-like by its energy
     less its mean potential, so the same state is the one filled."""
     p = _slab(nz=3, nxy=1, n_donors=1, seed=2)
