@@ -276,9 +276,9 @@ typedef struct {
  * nearest sigma; each gets its Ritz vector y = V s, an explicit FP64
  * residual |H y - theta y| and a Rayleigh-quotient refinement y^H H y with
  * the FP64 copy of H (the ham must have one: TBH_F64, or TBH_F32 built with
- * keep_f64).  Converged candidates within merge_tol are one eigenvalue; the
- * k distinct converged values nearest sigma (ties: lower value) are returned
- * in ascending order.  Without reorthogonalisation the recurrence loses
+ * keep_f64).  Converged candidates whose refined values lie within merge_tol
+ * are one eigenvalue; the k distinct converged values nearest sigma (by
+ * refined value; ties: lower value) are returned in ascending order.  Without reorthogonalisation the recurrence loses
  * orthogonality once Ritz values converge and repeats them ("ghost" copies,
  * Paige's analysis); each copy converges to the same eigenvalue and is merged
  * by merge_tol, so long runs (thousands of steps, memory permitting) reach
@@ -299,6 +299,110 @@ int tbh_lanczos_eigs(tbh_ham* h, const tbh_lanczos_opts* o, double* evals, doubl
  * calls with the same m and reorth, so repeated runs allocate nothing. */
 int tbh_lanczos_run(tbh_ham* h, const tbh_lanczos_opts* o, double* alpha, double* beta,
                     int32_t time_hx, tbh_lanczos_report* rep);
+
+/* ------------------------------------------------------------------------
+ * Block Lanczos (Sec. III-A, item 1 names "(block) Lanczos").
+ *
+ * A block of b orthonormal vectors replaces the single vector, so an
+ * eigenvalue of multiplicity up to b (degenerate states of a symmetric
+ * structure) appears with its full multiplicity, and a start block can carry
+ * several approximate eigenvectors (warm starts).  With Q_1 B_0 = X0:
+ *   W = H Q_j - Q_{j-1} B_j^T;  A_j = Q_j^T W;  W -= Q_j A_j;
+ *   twice { W -= Q (Q^T W) } over Q_1..Q_j;  Q_{j+1} B_{j+1} = W (QR);
+ * Rayleigh-Ritz on the block-tridiagonal T_m; Ritz vectors Y = Q S with
+ * explicit FP64 residuals |H y - theta y| and Rayleigh quotients (FP64 copy
+ * of H).  H.X and the basis are FP32 on the matrix cores; inner products,
+ * coefficients, QR factors, T and its eigensolve are FP64.  A QR column whose
+ * remainder is at most defl_tol |H| is deflated and replaced by a SplitMix64
+ * vector (counter ((j b + i) << 32) + row) orthogonalised against the basis.
+ * Real H only (TBH_F32 built with multi_vector = 1 and keep_f64 = 1).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double sigma;          /* target energy (eV) */
+    int32_t block;         /* block size b: 16, 32 or 64 */
+    int32_t steps;         /* block steps m per run; m * b <= 2048 */
+    int32_t cycles;        /* runs at most; a later run restarts from the b Ritz vectors nearest sigma */
+    int32_t k;             /* Ritz pairs wanted, 1 <= k <= b; each copy of a repeated eigenvalue counts */
+    double res_tol;        /* converged iff |H y - theta y| <= res_tol, |y| = 1 (0 = 1e-4 eV) */
+    double defl_tol;       /* deflation threshold relative to |H| (0 = 1e-6) */
+    const double* x0_dev;  /* device [b][dim] FP64 start block (state-major), or NULL for a
+                              SplitMix64 block */
+    int32_t fold;          /* 0: Krylov space of H.  1: of (H - sigma)^2 (two H.X per block step):
+                              the pairs nearest sigma are then its smallest eigenvalues, so
+                              interior pairs next to a gap converge without spurious Ritz values
+                              in the gap; eigenvalues are the FP64 Rayleigh quotients of H */
+} tbh_block_lanczos_opts;
+
+typedef struct {
+    int32_t cycles;        /* runs made */
+    int32_t n_found;       /* converged pairs reported (<= k) */
+    int32_t deflated;      /* deflated QR columns over all runs */
+    double max_res;        /* largest residual among the reported pairs (eV) */
+    double seconds;        /* wall time of the call */
+    double hx_seconds;     /* device time of the multi-vector H.X launches */
+} tbh_block_lanczos_report;
+
+/* The k Ritz pairs nearest sigma.  Each run computes the b Ritz pairs
+ * nearest sigma; the call stops when the k of them nearest sigma (by Ritz
+ * value) have converged, or after o->cycles runs.  The k converged pairs
+ * nearest sigma are returned ascending by Rayleigh quotient (host [k]:
+ * evals = Ritz values, refined = Rayleigh quotients, res = residuals;
+ * evecs_dev: device [k][dim] FP64 unit vectors, or NULL); slots past
+ * n_found are NaN / 0, and the call returns TBH_ENOCONV.  Device memory:
+ * (m + 3) * dim * b * 4 bytes for the basis and work blocks plus b * dim * 8
+ * for the Ritz vectors. */
+int tbh_block_lanczos_eigs(tbh_ham* h, const tbh_block_lanczos_opts* o, double* evals, double* refined,
+                           double* res, double* evecs_dev, tbh_block_lanczos_report* rep);
+
+/* ------------------------------------------------------------------------
+ * Filtered subspace eigensolver for the states next to a gap (the
+ * self-consistent loop's eigen-solve, Sec. III-A items 1-3).
+ *
+ * With F = (H - sigma)^2 and sigma in the gap, the pairs nearest sigma are
+ * the smallest eigenvalues of F.  A block of b vectors is filtered by the
+ * scaled Chebyshev polynomial of F that damps [f_cut, f_max] (f_cut the
+ * largest F value the block represents, f_max from spectral bounds of H by
+ * 60 Lanczos steps), orthonormalised by Cholesky QR and rotated to the Ritz
+ * vectors of H on its span (Chebyshev-filtered subspace iteration: Zhou,
+ * Saad, Tiago, Chelikowsky, J. Comput. Phys. 219 (2006) 172).  Each degree
+ * costs two multi-vector H.X (FP32 on the matrix cores); Gram and
+ * Rayleigh-Ritz matrices and residual sums are FP64.  Real H built TBH_F32
+ * with multi_vector = 1.  x0_dev = NULL starts from a random block; pass the
+ * vectors of an earlier call (padded to b) to warm-start.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double sigma;          /* fold centre (eV): in the gap, nearer the wanted pairs than any other band */
+    int32_t block;         /* b: 16, 32 or 64 */
+    int32_t degree;        /* Chebyshev degree of each filter after the first (>= 1) */
+    int32_t degree_cold;   /* degree of the first filter from a random block */
+    int32_t max_iter;      /* filter iterations at most */
+    int32_t k;             /* pairs nearest sigma that must converge, 1 <= k <= b */
+    double res_tol;        /* |H y - theta y| / |y| <= res_tol (0 = 1e-4 eV) */
+    const double* x0_dev;  /* device [b][dim] FP64 start block (state-major), or NULL for a
+                              SplitMix64 block */
+} tbh_filter_opts;
+
+typedef struct {
+    int32_t iterations;    /* filter iterations made */
+    int32_t n_found;       /* converged pairs reported (<= k) */
+    double max_res;        /* largest residual among them (eV) */
+    double emin, emax;     /* spectral bounds used (eV) */
+    double seconds;
+} tbh_filter_report;
+
+/* The k converged pairs nearest sigma, ascending: evals (host [k]), res
+ * (host [k]), evecs_dev (device [k][dim] FP64 unit vectors, or NULL); slots
+ * past n_found are NaN / 0 and the call returns TBH_ENOCONV. */
+int tbh_filtered_eigs(tbh_ham* h, const tbh_filter_opts* o, double* evals, double* res, double* evecs_dev,
+                      tbh_filter_report* rep);
+
+/* The nc eigenpairs nearest sigma of the real symmetric n x n matrix A (host,
+ * row-major, n <= 2048) by the projected-matrix eigensolver of block Lanczos
+ * (FP64 Householder tridiagonalisation, bisection, inverse iteration,
+ * back-transformation on the context's device): theta (host [nc],
+ * ascending) and vecs (host [nc][n] orthonormal eigenvectors, or NULL). */
+int tbh_symm_eig_near(tbh_ctx* ctx, int32_t n, const double* A, double sigma, int32_t nc, double* theta,
+                      double* vecs);
 
 /* Eigenvalues (ascending) of the symmetric tridiagonal matrix with diagonal
  * diag[m] and off-diagonal off[m-1] (host arrays), by FP64 Sturm bisection
@@ -360,6 +464,24 @@ typedef struct {
     const int32_t* donor_atoms;  /* host [n_donors]: atoms carrying a +e donor ion */
     int32_t n_donors;         /* also the electron count (neutrality) */
     const double* v0;         /* host [dim] FP64 Lanczos start vector (complex interleaved) */
+    /* eigen-solve: 0 = Lanczos with full CGS2 (n_cand, lanczos_iter, res_tol as
+     * above); 1 = filtered subspace iteration (tbh_filtered_eigs) on a block of
+     * `block` vectors kept across steps (real H built with multi_vector = 1):
+     * the fold centre is three quarters of the way from the valence-band top
+     * estimate (e_vbm + max U) to the conduction-band bottom estimate (the
+     * previous step's lowest filled state, or e_cbm + min U); each step runs
+     * filters of degree filter_degree (filter_degree_cold on the first step,
+     * from a random block) until the k_states pairs nearest the centre have
+     * residual <= max(res_tol, 0.1 * the previous step's SCF residual), at
+     * least one and at most filter_max_iter per step; every state of the block
+     * takes part in the filling. */
+    int32_t eig_mode;
+    int32_t block;            /* 16, 32 or 64 */
+    int32_t filter_degree;
+    int32_t filter_degree_cold;
+    int32_t filter_max_iter;
+    int32_t k_states;         /* <= block */
+    double e_vbm;             /* bulk valence-band maximum (eV) */
 } tbh_scf_opts;
 
 typedef struct {
@@ -376,6 +498,7 @@ typedef struct {
     double u_min;             /* min U after the update (eV) */
     double sigma;             /* Lanczos target of the step (eV) */
     double seconds, eig_seconds, poisson_seconds;
+    int32_t fell_back;        /* 1 if this step abandoned a start potential for the zero start */
 } tbh_scf_report;
 
 /* The SCF object keeps h (which must outlive it, and must have an FP64 copy)
@@ -384,8 +507,40 @@ int tbh_scf_create(tbh_ham* h, const tbh_scf_opts* o, tbh_scf** out);
 int tbh_scf_destroy(tbh_scf* s);
 /* Set U (device [nz][ny][nx] FP64, eV), or NULL = 0 (the plain start). */
 int tbh_scf_set_potential(tbh_scf* s, const double* U_dev);
+/* Start potential of the loop (Sec. III-A starts it from a given potential).
+ *  kind 0: zero.
+ *  kind 1 (mean): U0 = U_bare + mean.
+ *  kind 2 (learned): U0 = U_bare + mean + scale * y, y = net(x) or, with
+ *    symmetrize, the average of op^-1 net(op x) over the four in-plane point
+ *    operations of the slab that map each sublattice onto itself (identity,
+ *    the (110) and (1-10) mirrors, the two-fold rotation about the atom at
+ *    the origin; needs nx = ny).  The input x (4 channels) is built on the
+ *    device: the donor count per node, the A- and B-sublattice occupation of
+ *    the nodes, and U_bare / feat_scale.
+ * U_bare is the electron potential energy of the donor charges alone (the
+ * loop's Poisson solve of its donor term, CG to 1e-12); mean (device FP32
+ * [nz][ny][nx]) and scale are the training mean and scale of U* - U_bare.
+ * The start is abandoned for the zero start (reported as fell_back by the
+ * step that does it) when a residual is not finite, the residual grows three
+ * steps in a row, or the first residual exceeds first_res_limit (0 = no
+ * limit). */
+typedef struct tbh_net tbh_net;
+typedef struct {
+    int32_t kind;             /* 0 zero, 1 mean, 2 learned */
+    tbh_net* net;             /* kind 2: 4 input channels, the loop's grid */
+    const float* mean_dev;    /* kinds 1, 2 */
+    double scale;             /* kind 2 */
+    double feat_scale;        /* kind 2 */
+    int32_t symmetrize;       /* kind 2 */
+    double first_res_limit;
+} tbh_scf_start;
+int tbh_scf_set_start(tbh_scf* s, const tbh_scf_start* start);
 /* Copy the current U into U_dev (device [nz][ny][nx] FP64). */
 int tbh_scf_get_potential(tbh_scf* s, double* U_dev);
+/* Electrons per atom of the last step's filling (device [n_atoms] FP64,
+ * caller's atom order): sum over the filled states of 2 f sum_alpha
+ * |psi(i, alpha)|^2. */
+int tbh_scf_get_density(tbh_scf* s, double* n_dev);
 /* One self-consistency step; rep (host) receives the step's report. */
 int tbh_scf_step(tbh_scf* s, tbh_scf_report* rep);
 /* Steps until converged or max_iter steps; TBH_ENOCONV if not converged. */
@@ -433,8 +588,6 @@ int tbh_batch_configure(tbh_batch* b, int32_t grid, int32_t remap);
  * [dz][dy][dx] then b[c_out].  Inputs are device FP32 [c_in][nz][ny][nx],
  * outputs device FP32 [nz][ny][nx].
  * ------------------------------------------------------------------------ */
-typedef struct tbh_net tbh_net;
-
 /* channels must be 32; dilations: host [n_layers] in 1..64, or NULL for the
  * default 4-layer (1, 2, 4, 1); grid = (nx, ny, nz). */
 int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, int32_t n_layers,

@@ -26,7 +26,9 @@ definitions; numpy's eigh serves as the dense eigensolver step.
 
 Deflation.  When W loses rank (an eigenspace of multiplicity above b, or an
 exactly invariant start block), the QR step is Gram-Schmidt column by column
-(twice), and a column whose remainder is at most defl_tol |H| is deflated:
+(twice), and a column whose remainder is at most defl_tol |H| (|H| the
+largest entry of the A_j and B_j so far; for the start block, its largest
+column norm) is deflated:
 its row of B_{j+1} is zero and its new basis vector is a pseudo-random vector
 orthogonalised against every basis vector so far.  The pseudo-random values
 come from the SplitMix64 generator (Steele, Lea and Flood, "Fast splittable
@@ -104,7 +106,7 @@ def block_lanczos(matvec, X0, m, reorth=True, defl_tol=1e-12):
     n, b = X0.shape
     dt = np.result_type(X0.dtype, np.float64)
     X0 = X0.astype(dt)
-    Q1, R0 = qr_deflate(X0, np.zeros((n, 0), dtype=dt), 0, np.abs(X0).max(), defl_tol)
+    Q1, R0 = qr_deflate(X0, np.zeros((n, 0), dtype=dt), 0, np.linalg.norm(X0, axis=0).max(), defl_tol)
     Qs = [Q1]
     As, Bs = [], [R0]
     Qprev = np.zeros((n, b), dtype=dt)

@@ -78,18 +78,23 @@ def tridiag_eig(alpha, beta):
 def select_converged(theta, res, refined, sigma, k, merge_tol=1e-6, res_tol=1e-4):
     """Distinct converged eigenvalues nearest sigma.
 
-    Converged candidates are clustered: sorted by value, a gap larger than
-    merge_tol starts a new cluster.  A cluster's representative is its
-    member with the smallest residual.  The k clusters nearest sigma (ties:
-    smaller value) are returned ascending as dict arrays."""
+    A candidate's value is its Rayleigh quotient with the FP64 H (``refined``;
+    for a converged pair it is within res^2 / gap of the eigenvalue, while
+    the raw Ritz value of a reduced-precision recurrence can be off by more
+    than merge_tol).  Converged candidates are clustered: sorted by value, a
+    gap larger than merge_tol starts a new cluster.  A cluster's
+    representative is its member with the smallest residual.  The k clusters
+    nearest sigma (ties: smaller value) are returned ascending as dict
+    arrays."""
     theta = np.asarray(theta)
+    val = np.asarray(refined)
     conv = np.flatnonzero(np.asarray(res) <= res_tol)
     if conv.size == 0:
         return dict(theta=np.zeros(0), refined=np.zeros(0), res=np.zeros(0), copies=np.zeros(0, int))
-    o = conv[np.argsort(theta[conv], kind="stable")]
+    o = conv[np.argsort(val[conv], kind="stable")]
     clusters = [[o[0]]]
     for a, b in zip(o[:-1], o[1:]):
-        if theta[b] - theta[a] > merge_tol:
+        if val[b] - val[a] > merge_tol:
             clusters.append([b])
         else:
             clusters[-1].append(b)
@@ -97,9 +102,9 @@ def select_converged(theta, res, refined, sigma, k, merge_tol=1e-6, res_tol=1e-4
     for cl in clusters:
         r = min(cl, key=lambda i: (res[i], i))
         reps.append((r, len(cl)))
-    reps.sort(key=lambda rc: (abs(theta[rc[0]] - sigma), theta[rc[0]]))
+    reps.sort(key=lambda rc: (abs(val[rc[0]] - sigma), val[rc[0]]))
     reps = reps[:k]
-    reps.sort(key=lambda rc: theta[rc[0]])
+    reps.sort(key=lambda rc: val[rc[0]])
     idx = np.array([r for r, _ in reps], dtype=int)
     return dict(theta=theta[idx], refined=np.asarray(refined)[idx], res=np.asarray(res)[idx],
                 copies=np.array([c for _, c in reps], dtype=int), index=idx)

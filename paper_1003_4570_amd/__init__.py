@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -70,6 +71,27 @@ class tbh_lanczos_report(C.Structure):
                 ("hx_seconds", C.c_double)]
 
 
+class tbh_block_lanczos_opts(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("block", C.c_int32), ("steps", C.c_int32), ("cycles", C.c_int32),
+                ("k", C.c_int32), ("res_tol", C.c_double), ("defl_tol", C.c_double), ("x0_dev", C.c_void_p),
+                ("fold", C.c_int32)]
+
+
+class tbh_block_lanczos_report(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("n_found", C.c_int32), ("deflated", C.c_int32),
+                ("max_res", C.c_double), ("seconds", C.c_double), ("hx_seconds", C.c_double)]
+
+
+class tbh_filter_opts(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("block", C.c_int32), ("degree", C.c_int32), ("degree_cold", C.c_int32),
+                ("max_iter", C.c_int32), ("k", C.c_int32), ("res_tol", C.c_double), ("x0_dev", C.c_void_p)]
+
+
+class tbh_filter_report(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_found", C.c_int32), ("max_res", C.c_double), ("emin", C.c_double),
+                ("emax", C.c_double), ("seconds", C.c_double)]
+
+
 class tbh_scf_opts(C.Structure):
     _fields_ = [("grid", C.c_int32 * 3), ("h_nm", C.c_double), ("eps_r", C.c_double),
                 ("T_K", C.c_double), ("mix_alpha", C.c_double), ("tol_eV", C.c_double),
@@ -77,7 +99,9 @@ class tbh_scf_opts(C.Structure):
                 ("n_cand", C.c_int32), ("lanczos_iter", C.c_int32), ("res_tol", C.c_double),
                 ("cg_tol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("donor_atoms", C.POINTER(C.c_int32)), ("n_donors", C.c_int32),
-                ("v0", C.POINTER(C.c_double))]
+                ("v0", C.POINTER(C.c_double)), ("eig_mode", C.c_int32), ("block", C.c_int32),
+                ("filter_degree", C.c_int32), ("filter_degree_cold", C.c_int32), ("filter_max_iter", C.c_int32),
+                ("k_states", C.c_int32), ("e_vbm", C.c_double)]
 
 
 class tbh_scf_report(C.Structure):
@@ -86,7 +110,12 @@ class tbh_scf_report(C.Structure):
                 ("electrons", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_res", C.c_double),
                 ("lanczos_steps", C.c_int32), ("u_min", C.c_double), ("sigma", C.c_double),
                 ("seconds", C.c_double),
-                ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double)]
+                ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double), ("fell_back", C.c_int32)]
+
+
+class tbh_scf_start(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("net", C.c_void_p), ("mean_dev", C.c_void_p), ("scale", C.c_double),
+                ("feat_scale", C.c_double), ("symmetrize", C.c_int32), ("first_res_limit", C.c_double)]
 
 
 _lib = None
@@ -117,6 +146,12 @@ _SIGS = [
     ("tbh_lanczos_run", C.c_int, [C.c_void_p, C.POINTER(tbh_lanczos_opts), C.c_void_p,
                                   C.c_void_p, C.c_int32, C.POINTER(tbh_lanczos_report)]),
     ("tbh_tridiag_eig", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("tbh_block_lanczos_eigs", C.c_int, [C.c_void_p, C.POINTER(tbh_block_lanczos_opts), C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.POINTER(tbh_block_lanczos_report)]),
+    ("tbh_filtered_eigs", C.c_int, [C.c_void_p, C.POINTER(tbh_filter_opts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(tbh_filter_report)]),
+    ("tbh_symm_eig_near", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_int32, C.c_void_p,
+                                    C.c_void_p]),
     ("tbh_poisson_solve", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
@@ -125,6 +160,8 @@ _SIGS = [
     ("tbh_scf_set_potential", C.c_int, [C.c_void_p, C.c_void_p]),
     ("tbh_scf_get_potential", C.c_int, [C.c_void_p, C.c_void_p]),
     ("tbh_scf_step", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_report)]),
+    ("tbh_scf_get_density", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("tbh_scf_set_start", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_start)]),
     ("tbh_scf_run", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(tbh_scf_report)]),
     ("tbh_apply_h_multi", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("tbh_batch_create", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
@@ -271,22 +308,24 @@ def tabulate_host(**kw):
     return table[:k].reshape(nu.value, no, no), table[k:].reshape(ns, no), keys
 
 
-class Context:
-    """A library context on one HIP device and stream."""
+class _Handle:
+    """A library object.  close() first closes the objects that depend on it
+    (an SCF loop before its Hamiltonian, everything before its Context), so
+    the library never reaches a destroyed parent, whatever order Python
+    finalises the objects in (reference cycles at interpreter exit)."""
 
-    def __init__(self, device: int = 0, stream=None):
-        import torch
-        self.device = device
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        self._stream = stream
-        h = C.c_void_p()
-        _check(lib().tbh_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
-        self.h = h
+    _destroy = ""
+
+    def _adopt(self, *parents):
+        self._deps = weakref.WeakSet()
+        for p in parents:
+            p._deps.add(self)
 
     def close(self):
+        for d in list(getattr(self, "_deps", ())):
+            d.close()
         if getattr(self, "h", None):
-            lib().tbh_ctx_destroy(self.h)
+            getattr(lib(), self._destroy)(self.h)
             self.h = None
 
     def __del__(self):
@@ -296,10 +335,30 @@ class Context:
             pass
 
 
-class Hamiltonian:
+class Context(_Handle):
+    """A library context on one HIP device and stream."""
+
+    _destroy = "tbh_ctx_destroy"
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._adopt()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = C.c_void_p()
+        _check(lib().tbh_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+
+class Hamiltonian(_Handle):
     """A device Hamiltonian built by tbh_build_hamiltonian."""
 
+    _destroy = "tbh_ham_destroy"
+
     def __init__(self, ctx: Context, handle):
+        self._adopt(ctx)
         self.ctx = ctx
         self.h = handle
         info = tbh_ham_info()
@@ -323,17 +382,6 @@ class Hamiltonian:
         if self.prec == TBH_F64 or f64:
             return torch.complex128 if self.is_complex else torch.float64
         return torch.complex64 if self.is_complex else torch.float32
-
-    def close(self):
-        if getattr(self, "h", None):
-            lib().tbh_ham_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def build_hamiltonian(ctx: Context, **kw) -> Hamiltonian:
@@ -474,6 +522,83 @@ def lanczos_eigs(ham: Hamiltonian, sigma: float, k: int, max_iter: int, v0, reor
     return out
 
 
+def block_lanczos_eigs(ham: Hamiltonian, sigma: float, k: int, block: int, steps: int, cycles: int = 1,
+                       x0=None, res_tol: float = 0.0, defl_tol: float = 0.0, want_vectors: bool = False,
+                       allow_partial: bool = True, fold: bool = False):
+    """The k converged Ritz pairs nearest sigma by block Lanczos (each copy of
+    a repeated eigenvalue counts).  x0: None (SplitMix64 block) or a [block,
+    dim] float64 device tensor.  fold: Krylov space of (H - sigma)^2.
+    Returns dict(evals, refined, res, report[, vectors [n_found, dim] float64
+    device tensor])."""
+    import torch
+    if x0 is not None:
+        if not (isinstance(x0, torch.Tensor) and x0.is_cuda and x0.dtype == torch.float64 and x0.is_contiguous()
+                and x0.numel() == block * ham.dim):
+            raise TypeError("x0 must be a contiguous float64 device tensor [block, dim]")
+    o = tbh_block_lanczos_opts(float(sigma), int(block), int(steps), int(cycles), int(k), float(res_tol),
+                               float(defl_tol), None if x0 is None else C.c_void_p(x0.data_ptr()),
+                               int(bool(fold)))
+    ev = np.zeros(k)
+    rf = np.zeros(k)
+    rs = np.zeros(k)
+    vec = None
+    if want_vectors:
+        vec = torch.zeros((k, ham.dim), dtype=torch.float64, device=f"cuda:{ham.ctx.device}")
+    rep = tbh_block_lanczos_report()
+    rc = lib().tbh_block_lanczos_eigs(ham.h, C.byref(o), ev.ctypes.data, rf.ctypes.data, rs.ctypes.data,
+                                      None if vec is None else C.c_void_p(vec.data_ptr()), C.byref(rep))
+    if rc != TBH_OK and not (allow_partial and rc == TBH_ENOCONV):
+        _check(rc)
+    r = {f: getattr(rep, f) for f, _ in rep._fields_}
+    n = r["n_found"]
+    out = dict(evals=ev[:n], refined=rf[:n], res=rs[:n], report=r, status=rc)
+    if vec is not None:
+        out["vectors"] = vec[:n]
+    return out
+
+
+def filtered_eigs(ham: Hamiltonian, sigma: float, k: int, block: int = 64, degree: int = 20, degree_cold: int = 60,
+                  max_iter: int = 50, res_tol: float = 0.0, x0=None, want_vectors: bool = False,
+                  allow_partial: bool = True):
+    """The k converged pairs nearest sigma (sigma in a gap) by Chebyshev-filtered
+    subspace iteration on (H - sigma)^2.  x0: None or a [block, dim] float64
+    device tensor.  Returns dict(evals, res, report[, vectors])."""
+    import torch
+    if x0 is not None and not (isinstance(x0, torch.Tensor) and x0.is_cuda and x0.dtype == torch.float64
+                               and x0.is_contiguous() and x0.numel() == block * ham.dim):
+        raise TypeError("x0 must be a contiguous float64 device tensor [block, dim]")
+    o = tbh_filter_opts(float(sigma), int(block), int(degree), int(degree_cold), int(max_iter), int(k),
+                        float(res_tol), None if x0 is None else C.c_void_p(x0.data_ptr()))
+    ev = np.zeros(k)
+    rs = np.zeros(k)
+    vec = None
+    if want_vectors:
+        vec = torch.zeros((k, ham.dim), dtype=torch.float64, device=f"cuda:{ham.ctx.device}")
+    rep = tbh_filter_report()
+    rc = lib().tbh_filtered_eigs(ham.h, C.byref(o), ev.ctypes.data, rs.ctypes.data,
+                                 None if vec is None else C.c_void_p(vec.data_ptr()), C.byref(rep))
+    if rc != TBH_OK and not (allow_partial and rc == TBH_ENOCONV):
+        _check(rc)
+    r = {f: getattr(rep, f) for f, _ in rep._fields_}
+    n = r["n_found"]
+    out = dict(evals=ev[:n], res=rs[:n], report=r, status=rc)
+    if vec is not None:
+        out["vectors"] = vec[:n]
+    return out
+
+
+def symm_eig_near(ctx: Context, A, sigma: float, nc: int):
+    """The nc eigenpairs nearest sigma of the real symmetric matrix A (host
+    array) with the device's projected-matrix eigensolver.  Returns (theta
+    ascending, vectors [nc, n])."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    th = np.zeros(nc)
+    V = np.zeros((nc, n))
+    _check(lib().tbh_symm_eig_near(ctx.h, n, A.ctypes.data, float(sigma), int(nc), th.ctypes.data, V.ctypes.data))
+    return th, V
+
+
 def tridiag_eig(ctx: Context, diag, off):
     """Eigenvalues (ascending) of a symmetric tridiagonal matrix, FP64
     bisection on the device."""
@@ -492,23 +617,31 @@ def poisson_solve(ctx: Context, grid, h_nm, eps_r, rho, phi=None, rel_tol=1e-10,
     import torch
     if phi is None:
         phi = torch.zeros_like(rho)
+    for t in (rho, phi):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == int(np.prod(grid))):
+            raise TypeError("rho and phi must be contiguous float64 device tensors of the grid's size")
     g = (C.c_int32 * 3)(*[int(v) for v in grid])
     it = C.c_int32(0)
     rr = C.c_double(0.0)
     rc = lib().tbh_poisson_solve(ctx.h, g, float(h_nm), float(eps_r), C.c_void_p(rho.data_ptr()),
-                                 C.c_void_p(phi.data_ptr()), float(rel_tol), int(max_iter),
-                                 C.byref(it), C.byref(rr))
+            C.c_void_p(phi.data_ptr()), float(rel_tol), int(max_iter),
+            C.byref(it), C.byref(rr))
     if rc not in (TBH_OK, TBH_ENOCONV):
         _check(rc)
     return phi, it.value, rr.value
 
 
-class SCF:
+class SCF(_Handle):
     """Self-consistent Schrodinger-Poisson loop on a device Hamiltonian."""
+
+    _destroy = "tbh_scf_destroy"
 
     def __init__(self, ham: Hamiltonian, grid, donor_atoms, v0, sigma_mid, e_cbm, h_nm, eps_r=11.7,
                  T_K=4.0, mix_alpha=0.1, tol_eV=1e-4, n_cand=48, lanczos_iter=600, res_tol=1e-4,
-                 cg_tol=1e-12, cg_max_iter=20000, fermi_fixed=None):
+                 cg_tol=1e-12, cg_max_iter=20000, fermi_fixed=None, eig_mode=0, block=64, filter_degree=20,
+                 filter_degree_cold=60, filter_max_iter=20, k_states=40, e_vbm=float("nan")):
+        self._adopt(ham)
         self.ham = ham
         self.grid = tuple(int(g) for g in grid)
         self._donors = np.ascontiguousarray(donor_atoms, dtype=np.int32)
@@ -518,7 +651,9 @@ class SCF:
                          float("nan") if fermi_fixed is None else float(fermi_fixed),
                          int(n_cand), int(lanczos_iter), float(res_tol), float(cg_tol),
                          int(cg_max_iter), _p(self._donors, C.c_int32), int(self._donors.size),
-                         self._v0.ctypes.data_as(C.POINTER(C.c_double)))
+                         self._v0.ctypes.data_as(C.POINTER(C.c_double)), int(eig_mode), int(block),
+                         int(filter_degree), int(filter_degree_cold), int(filter_max_iter), int(k_states),
+                         float(e_vbm))
         h = C.c_void_p()
         _check(lib().tbh_scf_create(ham.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -534,6 +669,26 @@ class SCF:
         _check(lib().tbh_scf_get_potential(self.h, C.c_void_p(U.data_ptr())))
         return U
 
+    def set_start(self, kind, net=None, mean=None, scale=0.0, feat_scale=1.0, symmetrize=True,
+                  first_res_limit=0.0):
+        """Start potential built on the device (tbh_scf_set_start): kind
+        "zero", "mean" (U_bare + mean) or "learned" (U_bare + mean + scale *
+        the network's output, averaged over the point operations).  mean:
+        float32 device tensor [nz, ny, nx]."""
+        k = {"zero": 0, "mean": 1, "learned": 2}[kind]
+        if mean is not None:
+            self._mean = mean.float().contiguous()
+        o = tbh_scf_start(k, None if net is None else net.h, None if mean is None else C.c_void_p(self._mean.data_ptr()),
+                          float(scale), float(feat_scale), int(bool(symmetrize)), float(first_res_limit))
+        _check(lib().tbh_scf_set_start(self.h, C.byref(o)))
+
+    def density(self):
+        """Electrons per atom of the last step (float64 device tensor, caller order)."""
+        import torch
+        n = torch.empty(self.ham.info["n_atoms"], dtype=torch.float64, device=f"cuda:{self.ham.ctx.device}")
+        _check(lib().tbh_scf_get_density(self.h, C.c_void_p(n.data_ptr())))
+        return n
+
     def step(self):
         r = tbh_scf_report()
         _check(lib().tbh_scf_step(self.h, C.byref(r)))
@@ -546,16 +701,6 @@ class SCF:
             _check(rc)
         return {k: getattr(r, k) for k, _ in tbh_scf_report._fields_}
 
-    def close(self):
-        if getattr(self, "h", None):
-            lib().tbh_scf_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def _check_mv(ham, t, nrhs):
@@ -580,15 +725,18 @@ def apply_h_multi(ham: Hamiltonian, X, Y=None):
     return Y
 
 
-class Batch:
+class Batch(_Handle):
     """Many Hamiltonians' multi-vector products in one persistent launch
     (captured in a HIP graph)."""
+
+    _destroy = "tbh_batch_destroy"
 
     def __init__(self, ctx: Context, hams, Xs, Ys):
         nrhs = Xs[0].shape[-1]
         for h, x, y in zip(hams, Xs, Ys):
             _check_mv(h, x, nrhs)
             _check_mv(h, y, nrhs)
+        self._adopt(ctx, *hams)
         self.ctx, self.hams, self.Xs, self.Ys = ctx, list(hams), list(Xs), list(Ys)
         n = len(hams)
         H = (C.c_void_p * n)(*[h.h for h in hams])
@@ -615,24 +763,17 @@ class Batch:
                                         C.byref(g), C.byref(r), C.byref(ms)))
         return dict(grid=g.value, remap=r.value, ms=ms.value)
 
-    def close(self):
-        if getattr(self, "h", None):
-            lib().tbh_batch_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
-class Net:
+class Net(_Handle):
     """The convolutional start-potential surrogate (device kernels).
     grid = (nx, ny, nz); inputs are float32 device tensors [in_channels, nz,
     ny, nx] (or [nz, ny, nx] for one channel), outputs [nz, ny, nx]."""
 
+    _destroy = "tbh_net_destroy"
+
     def __init__(self, ctx: Context, grid, channels=32, in_channels=1, dilations=(1, 2, 4, 1)):
+        self._adopt(ctx)
         self.ctx = ctx
         self.grid = tuple(int(g) for g in grid)
         self.in_channels = int(in_channels)
@@ -700,16 +841,6 @@ class Net:
         _check(lib().tbh_net_train_step(self.h, X, T, n, float(lr), C.byref(loss)))
         return loss.value
 
-    def close(self):
-        if getattr(self, "h", None):
-            lib().tbh_net_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
 
 def flatten_params(params):

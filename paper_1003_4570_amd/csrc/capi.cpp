@@ -52,6 +52,31 @@ int choose_rows(int n_o, bool cplx_h, int prec, int64_t n_atoms, int lanes) {
 }  // namespace
 }  // namespace tbh
 
+namespace tbh {
+
+void retain(Ctx* c) { c->refs.fetch_add(1); }
+
+void release(Ctx* c) {
+    if (c->refs.fetch_sub(1) != 1) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    delete static_cast<tbh_ctx*>(c);
+}
+
+void retain(Ham* h) { h->refs.fetch_add(1); }
+
+void release(Ham* h) {
+    if (h->refs.fetch_sub(1) != 1) return;
+    Ctx* c = h->ctx;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete static_cast<tbh_ham*>(h);
+    release(c);
+}
+
+}  // namespace tbh
+
 namespace {
 
 // y = H x with x, y in the caller's atom order: straight through when the
@@ -106,9 +131,7 @@ int tbh_ctx_create(int device, void* stream, tbh_ctx** out) {
 int tbh_ctx_destroy(tbh_ctx* c) {
     return guard([&] {
         if (!c) return;
-        (void)hipSetDevice(c->device);
-        if (c->stream) (void)hipStreamSynchronize(c->stream);
-        delete c;
+        tbh::release(c);
     });
 }
 
@@ -303,6 +326,7 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         } else {
             TBH_HIP(hipMemcpy(h->nbr_d.p, M.nbr.data(), M.nbr.size() * 4, hipMemcpyHostToDevice));
         }
+        tbh::retain(ctx);
         *out = h.release();
     });
 }
@@ -310,10 +334,7 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
 int tbh_ham_destroy(tbh_ham* h) {
     return guard([&] {
         if (!h) return;
-        (void)hipSetDevice(h->ctx->device);
-        if (h->ctx->stream) (void)hipStreamSynchronize(h->ctx->stream);
-        else (void)hipDeviceSynchronize();
-        delete h;
+        tbh::release(h);
     });
 }
 

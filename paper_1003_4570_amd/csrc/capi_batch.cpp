@@ -12,6 +12,7 @@ using tbh::guard;
 
 struct tbh_batch {
     tbh::Ctx* ctx = nullptr;
+    std::vector<tbh::Ham*> hams;   // referenced (retained) for the batch's lifetime
     int nrhs = 16, n_o = 0;
     bool cplx_h = false;
     std::vector<tbh::MvDesc> host;
@@ -131,6 +132,11 @@ int tbh_batch_create(tbh_ctx* ctx, tbh_ham* const* hams, int32_t count, const fl
         b->grid = int(std::min<int64_t>(default_grid(ctx->device), b->total));
         b->remap = 1;
         b->capture();
+        tbh::retain(ctx);
+        for (int i = 0; i < count; ++i) {
+            tbh::retain(hams[i]);
+            b->hams.push_back(hams[i]);
+        }
         *out = b.release();
     });
 }
@@ -138,9 +144,13 @@ int tbh_batch_create(tbh_ctx* ctx, tbh_ham* const* hams, int32_t count, const fl
 int tbh_batch_destroy(tbh_batch* b) {
     return guard([&] {
         if (!b) return;
-        (void)hipSetDevice(b->ctx->device);
-        (void)hipStreamSynchronize(b->ctx->stream);
+        tbh::Ctx* c = b->ctx;
+        std::vector<tbh::Ham*> hams = b->hams;
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
         delete b;
+        for (tbh::Ham* h : hams) tbh::release(h);
+        tbh::release(c);
     });
 }
 

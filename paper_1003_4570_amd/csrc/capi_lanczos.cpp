@@ -17,18 +17,22 @@ struct Cand {
     int c;
 };
 
-// Distinct converged values nearest sigma (see tbh_lanczos_eigs).
+// Distinct converged values nearest sigma (see tbh_lanczos_eigs).  A
+// candidate's value is its FP64 Rayleigh quotient: for a converged pair it is
+// within res^2 / gap of the eigenvalue, while the raw Ritz value of an FP32
+// recurrence can be off by more than merge_tol, which would keep two copies
+// of one eigenvalue apart.
 std::vector<std::pair<int, int>> select_converged(const std::vector<Cand>& cs, double sigma, int k,
                                                   double res_tol, double merge_tol) {
     std::vector<int> conv;
     for (int i = 0; i < int(cs.size()); ++i)
         if (cs[i].res <= res_tol) conv.push_back(i);
-    std::stable_sort(conv.begin(), conv.end(), [&](int a, int b) { return cs[a].theta < cs[b].theta; });
+    std::stable_sort(conv.begin(), conv.end(), [&](int a, int b) { return cs[a].refined < cs[b].refined; });
     std::vector<std::pair<int, int>> reps;  // (representative, copies)
     size_t s = 0;
     while (s < conv.size()) {
         size_t e = s + 1;
-        while (e < conv.size() && cs[conv[e]].theta - cs[conv[e - 1]].theta <= merge_tol) ++e;
+        while (e < conv.size() && cs[conv[e]].refined - cs[conv[e - 1]].refined <= merge_tol) ++e;
         int best = conv[s];
         for (size_t t = s; t < e; ++t) {
             const int i = conv[t];
@@ -38,13 +42,13 @@ std::vector<std::pair<int, int>> select_converged(const std::vector<Cand>& cs, d
         s = e;
     }
     std::stable_sort(reps.begin(), reps.end(), [&](const auto& a, const auto& b) {
-        const double da = std::fabs(cs[a.first].theta - sigma), db = std::fabs(cs[b.first].theta - sigma);
+        const double da = std::fabs(cs[a.first].refined - sigma), db = std::fabs(cs[b.first].refined - sigma);
         if (da != db) return da < db;
-        return cs[a.first].theta < cs[b.first].theta;
+        return cs[a.first].refined < cs[b.first].refined;
     });
     if (int(reps.size()) > k) reps.resize(k);
     std::stable_sort(reps.begin(), reps.end(),
-                     [&](const auto& a, const auto& b) { return cs[a.first].theta < cs[b.first].theta; });
+                     [&](const auto& a, const auto& b) { return cs[a.first].refined < cs[b.first].refined; });
     return reps;
 }
 

@@ -57,6 +57,7 @@ int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, int32_t 
         std::vector<float> z(n->n_params, 0.f);
         TBH_HIP(hipMemcpy(n->w32.p, z.data(), z.size() * 4, hipMemcpyHostToDevice));
         n->sync_half();
+        tbh::retain(ctx);
         *out = n.release();
     });
 }
@@ -64,9 +65,11 @@ int tbh_net_create(tbh_ctx* ctx, int32_t channels, int32_t in_channels, int32_t 
 int tbh_net_destroy(tbh_net* n) {
     return guard([&] {
         if (!n) return;
-        (void)hipSetDevice(n->ctx->device);
-        (void)hipStreamSynchronize(n->ctx->stream);
+        tbh::Ctx* c = n->ctx;
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
         delete n;
+        tbh::release(c);
     });
 }
 

@@ -46,15 +46,18 @@ int tbh_scf_create(tbh_ham* h, const tbh_scf_opts* o, tbh_scf** out) {
         TBH_REQUIRE(h && o && out, "null argument");
         TBH_HIP(hipSetDevice(h->ctx->device));
         *out = new tbh_scf(h, *o);
+        tbh::retain(h);
     });
 }
 
 int tbh_scf_destroy(tbh_scf* s) {
     return guard([&] {
         if (!s) return;
-        (void)hipSetDevice(s->h->ctx->device);
-        (void)hipStreamSynchronize(s->h->ctx->stream);
+        tbh::Ham* h = s->h;
+        (void)hipSetDevice(h->ctx->device);
+        (void)hipStreamSynchronize(h->ctx->stream);
         delete s;
+        tbh::release(h);
     });
 }
 
@@ -66,12 +69,34 @@ int tbh_scf_set_potential(tbh_scf* s, const double* U_dev) {
     });
 }
 
+int tbh_scf_set_start(tbh_scf* s, const tbh_scf_start* start) {
+    return guard([&] {
+        TBH_REQUIRE(s && start, "null argument");
+        TBH_HIP(hipSetDevice(s->h->ctx->device));
+        s->set_start(*start);
+    });
+}
+
 int tbh_scf_get_potential(tbh_scf* s, double* U_dev) {
     return guard([&] {
         TBH_REQUIRE(s && U_dev, "null argument");
         TBH_HIP(hipSetDevice(s->h->ctx->device));
         TBH_HIP(hipMemcpyAsync(U_dev, s->U.p, s->n_nodes * 8, hipMemcpyDeviceToDevice, s->h->ctx->stream));
         TBH_HIP(hipStreamSynchronize(s->h->ctx->stream));
+    });
+}
+
+int tbh_scf_get_density(tbh_scf* s, double* n_dev) {
+    return guard([&] {
+        TBH_REQUIRE(s && n_dev, "null argument");
+        TBH_REQUIRE(s->iterations > 0, "no step has been made");
+        TBH_HIP(hipSetDevice(s->h->ctx->device));
+        hipStream_t st = s->h->ctx->stream;
+        if (s->h->permuted)
+            tbh::rows_to_caller(st, s->h->n, s->h->perm_d.as<int64_t>(), 8, s->n_atoms_d.p, n_dev);
+        else
+            TBH_HIP(hipMemcpyAsync(n_dev, s->n_atoms_d.p, size_t(s->h->n) * 8, hipMemcpyDeviceToDevice, st));
+        TBH_HIP(hipStreamSynchronize(st));
     });
 }
 

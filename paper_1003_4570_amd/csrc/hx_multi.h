@@ -14,6 +14,7 @@ struct MvDesc {
     float* y;
     int64_t atom_begin;     // offset of this instance in the concatenated atom range
     int64_t n_atoms;
+    double shift = 0.0;     // added to every diagonal element: Y = (H + shift) X
 };
 
 bool mv_supported(int n_o, int nrhs);

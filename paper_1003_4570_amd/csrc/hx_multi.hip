@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
         const int64_t atom = g - d.atom_begin;
         // stage the prefetched blocks (bonds 0..3, on-site + potential on its
         // diagonal) into LDS
-        const float u = d.pot ? float(d.pot[atom]) : 0.f;
+        const float u = float((d.pot ? d.pot[atom] : 0.0) + d.shift);
 #pragma unroll
         for (int p = 0; p < PV; ++p) {
             const int c = lane + p * 64;
@@ -242,8 +242,13 @@ void launch_no(int nrhs, const MvDesc* desc, int n_inst, int64_t total, int grid
         hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 16>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, remap);
     else if (nrhs == 32)
         hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 32>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, remap);
+    else if constexpr (!CPLX)
+        if (nrhs == 64)
+            hipLaunchKernelGGL((k_hx_mv<CPLX, NO, 64>), dim3(grid), dim3(64), 0, s, desc, n_inst, total, remap);
+        else
+            throw Error(TBH_EINVAL, "multi-vector H.X supports nrhs = 16, 32 (or 64 for a real H)");
     else
-        throw Error(TBH_EINVAL, "multi-vector H.X supports nrhs = 16 or 32");
+        throw Error(TBH_EINVAL, "multi-vector H.X supports nrhs = 16 or 32 for a complex H");
 }
 
 }  // namespace

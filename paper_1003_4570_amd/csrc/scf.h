@@ -1,6 +1,7 @@
 // Schrodinger-Poisson internals shared by scf.hip and the C ABI.
 #pragma once
 
+#include "block_lanczos.h"
 #include "lanczos.h"
 #include "tbh_internal.h"
 
@@ -12,10 +13,21 @@ struct PoissonWork {
     void ensure(int64_t n);
 };
 
+// device scratch of one CG solve: r, p, Ap [n] FP64; part [2 * 4096]
+// block partial sums; s [8] scalar state
+struct PoissonBufs {
+    double *r, *p, *Ap, *part, *s;
+};
+constexpr int64_t POISSON_PART = 2 * 4096;
+constexpr int64_t POISSON_SCAL = 8;
+
 // FP64 CG for -Lap_h x = b on the grid (periodic x, y; Dirichlet z); x holds
 // the initial guess on entry and the solution on exit.
 void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, const double* b, double* x,
                 double rel_tol, int max_iter, int* iters, double* rel_res);
+// the same on caller-provided scratch (no allocation)
+void poisson_cg_bufs(hipStream_t st, const PoissonBufs& W, const int grid[3], double h, const double* b,
+                     double* x, double rel_tol, int max_iter, int* iters, double* rel_res);
 
 struct Scf {
     Ham* h;
@@ -29,6 +41,20 @@ struct Scf {
     PoissonWork pw;
     std::shared_ptr<LzWork> lz;
     RitzOut ritz;
+    // start potential (tbh_scf_set_start) and the fallback to the zero start
+    DevBuf dmap_d, mask_d, ubare_d, xin_d, xop_d, yop_d, acc_d;
+    bool have_ubare = false;
+    int start_kind = 0;
+    double first_res_limit = 0.0;
+    int since_start = 0, grow = 0;
+    double prev_res = 0.0;
+    void compute_ubare();
+    void set_start(const tbh_scf_start& st);
+    // filtered subspace eigen-solve (eig_mode 1)
+    std::shared_ptr<BlWork> blw;
+    std::shared_ptr<FsWork> fs;
+    bool fs_warm = false, have_bounds = false;
+    double emin_b = 0.0, emax_b = 0.0, last_res = 0.0;
     Scf(Ham* h, const tbh_scf_opts& o);
     void set_potential(const double* U_dev);
     void step(tbh_scf_report& rep);

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <limits>
 
+#include "conv.h"
 #include "lanczos.h"
 #include "scf.h"
 
@@ -302,7 +303,7 @@ __global__ void k_mix(int64_t n, const double* phi, double* U, double alpha, dou
 }
 
 __global__ void k_mix_reduce(const double* part, int64_t nb, double* out) {
-    double mx = 0.0, mn = INFINITY;
+    double mx = -INFINITY, mn = INFINITY;
     for (int64_t b = threadIdx.x; b < nb; b += TPB) {
         mx = fmax(mx, part[2 * b]);
         mn = fmin(mn, part[2 * b + 1]);
@@ -315,12 +316,17 @@ __global__ void k_mix_reduce(const double* part, int64_t nb, double* out) {
     }
 }
 
-__global__ void k_min(int64_t n, const double* U, double* part) {
-    double mn = INFINITY;
-    GRID_LOOP(i, n) mn = fmin(mn, U[i]);
+// partial max and min of U (reduced by k_mix_reduce into out[0], out[1])
+__global__ void k_minmax(int64_t n, const double* U, double* part) {
+    double mn = INFINITY, mx = -INFINITY;
+    GRID_LOOP(i, n) {
+        mn = fmin(mn, U[i]);
+        mx = fmax(mx, U[i]);
+    }
+    const double a = block_max1(mx);
     const double b = block_min1(mn);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = 0.0;
+        part[2 * blockIdx.x] = a;
         part[2 * blockIdx.x + 1] = b;
     }
 }
@@ -332,6 +338,57 @@ __global__ void k_gather_atoms(int64_t n_atoms, const int64_t* node, const doubl
 int64_t grid_for(int64_t n) {
     int64_t g = (n + TPB - 1) / TPB;
     return g < 1 ? 1 : (g > 4096 ? 4096 : g);
+}
+
+// the network's input maps: donor count, A mask, B mask, U_bare / feat_scale
+__global__ void k_start_inputs(int64_t n, const float* dmap, const float* mask, const double* ubare,
+                               double inv_fs, float* x) {
+    GRID_LOOP(i, n) {
+        x[i] = dmap[i];
+        x[n + i] = mask[i];
+        x[2 * n + i] = mask[n + i];
+        x[3 * n + i] = float(ubare[i] * inv_fs);
+    }
+}
+
+// out[c][z][y][x] = in[c][z][Y][X], (Y, X) the in-plane point operation op
+// (0 identity, 1 (110) mirror, 2 two-fold rotation, 3 (1-10) mirror; each
+// its own inverse); nx == ny for the mirrors
+__global__ void k_point_op(int64_t n, int channels, int nx, int ny, int op, const float* in, float* out) {
+    const int64_t total = n * channels;
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < total; i += int64_t(gridDim.x) * TPB) {
+        const int64_t c = i / n, v = i % n;
+        const int x = int(v % nx), y = int((v / nx) % ny);
+        const int64_t zb = v - (int64_t(y) * nx + x);
+        int X = x, Y = y;
+        if (op == 1) {
+            X = y;
+            Y = x;
+        } else if (op == 2) {
+            X = (nx - x) % nx;
+            Y = (ny - y) % ny;
+        } else if (op == 3) {
+            X = (ny - y) % ny;
+            Y = (nx - x) % nx;
+        }
+        out[i] = in[c * n + zb + int64_t(Y) * nx + X];
+    }
+}
+
+// acc (+)= y
+__global__ void k_accum(int64_t n, const float* y, float* acc, int first) {
+    GRID_LOOP(i, n) acc[i] = first ? y[i] : acc[i] + y[i];
+}
+
+// U = U_bare + mean + scale * acc
+__global__ void k_start_combine(int64_t n, const double* ubare, const float* mean, const float* acc, double scale,
+                                double* U) {
+    GRID_LOOP(i, n) {
+        double u = ubare[i];
+        if (mean) u += double(mean[i]);
+        if (acc) u += scale * double(acc[i]);
+        U[i] = u;
+    }
 }
 
 }  // namespace
@@ -350,31 +407,30 @@ void PoissonWork::ensure(int64_t n) {
     this->n = n;
 }
 
-void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, const double* b, double* x,
-                double rel_tol, int max_iter, int* iters, double* rel_res) {
+void poisson_cg_bufs(hipStream_t st, const PoissonBufs& W, const int grid[3], double h, const double* b,
+                     double* x, double rel_tol, int max_iter, int* iters, double* rel_res) {
     const int nx = grid[0], ny = grid[1], nz = grid[2];
     const int64_t n = int64_t(nx) * ny * nz;
-    W.ensure(n);
     const double inv_h2 = 1.0 / (h * h);
     const int64_t g = grid_for(n);
-    double* part = W.part.as<double>();
-    double* s = W.s.as<double>();
-    // r = A x (into r), then r = b - r, p = r
-    hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, x, W.r.as<double>(),
+    double* part = W.part;
+    double* s = W.s;
+    // r = A x (into r), then r = b - r, p = r; every scratch value is written
+    // before it is read, so nothing needs clearing between calls
+    hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, x, W.r,
                        (double*)nullptr, (const double*)nullptr);
-    hipLaunchKernelGGL(k_cg_init, dim3(g), dim3(TPB), 0, st, n, b, W.r.as<double>(), W.p.as<double>(), part);
+    hipLaunchKernelGGL(k_cg_init, dim3(g), dim3(TPB), 0, st, n, b, W.r, W.p, part);
     hipLaunchKernelGGL(k_cg_init_scalars, dim3(1), dim3(TPB), 0, st, part, g, s, rel_tol);
     double hs[CG_NS];
     const int chunk = 25;
     for (int it = 0; it < max_iter; it += chunk) {
         for (int k = 0; k < chunk; ++k) {
-            hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, W.p.as<double>(),
-                               W.Ap.as<double>(), part, s + CG_DONE);
+            hipLaunchKernelGGL(k_stencil, dim3(g), dim3(TPB), 0, st, nx, ny, nz, inv_h2, W.p, W.Ap, part,
+                               s + CG_DONE);
             hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(TPB), 0, st, part, g, s);
-            hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, st, n, x, W.r.as<double>(), W.p.as<double>(),
-                               W.Ap.as<double>(), s, part);
+            hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(TPB), 0, st, n, x, W.r, W.p, W.Ap, s, part);
             hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(TPB), 0, st, part, g, s, rel_tol, max_iter);
-            hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(TPB), 0, st, n, W.r.as<double>(), W.p.as<double>(), s);
+            hipLaunchKernelGGL(k_cg_p, dim3(g), dim3(TPB), 0, st, n, W.r, W.p, s);
         }
         TBH_HIP(hipMemcpyAsync(hs, s, sizeof(hs), hipMemcpyDeviceToHost, st));
         TBH_HIP(hipStreamSynchronize(st));
@@ -383,6 +439,15 @@ void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, con
     TBH_HIP(hipGetLastError());
     if (iters) *iters = int(hs[CG_ITERS]);
     if (rel_res) *rel_res = hs[CG_REL];
+}
+
+void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, const double* b, double* x,
+                double rel_tol, int max_iter, int* iters, double* rel_res) {
+    const int64_t n = int64_t(grid[0]) * grid[1] * grid[2];
+    W.ensure(n);
+    const PoissonBufs v{W.r.as<double>(), W.p.as<double>(), W.Ap.as<double>(), W.part.as<double>(),
+                        W.s.as<double>()};
+    poisson_cg_bufs(st, v, grid, h, b, x, rel_tol, max_iter, iters, rel_res);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +462,15 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     }
     TBH_REQUIRE(o.h_nm > 0 && o.eps_r > 0 && o.T_K >= 0, "h_nm, eps_r must be positive, T_K >= 0");
     TBH_REQUIRE(o.mix_alpha > 0 && o.mix_alpha <= 1, "mix_alpha must be in (0, 1]");
-    TBH_REQUIRE(o.n_cand >= 1 && o.lanczos_iter >= o.n_cand, "need n_cand >= 1 and lanczos_iter >= n_cand");
+    TBH_REQUIRE(o.eig_mode == 0 || o.eig_mode == 1, "eig_mode must be 0 (Lanczos) or 1 (filtered block)");
+    if (o.eig_mode == 0)
+        TBH_REQUIRE(o.n_cand >= 1 && o.lanczos_iter >= o.n_cand, "need n_cand >= 1 and lanczos_iter >= n_cand");
+    else
+        TBH_REQUIRE((o.block == 16 || o.block == 32 || o.block == 64) && o.k_states >= 1 && o.k_states <= o.block &&
+                        o.filter_degree >= 1 && o.filter_degree_cold >= 1 && o.filter_max_iter >= 1 &&
+                        h->has_mv && !h->cplx_h,
+                    "filtered eigen-solve: block 16/32/64, 1 <= k_states <= block, degrees and filter_max_iter >= 1, "
+                    "and a real H built with multi_vector = 1");
     TBH_REQUIRE(o.n_donors >= 0 && (o.n_donors == 0 || o.donor_atoms), "bad donor list");
     TBH_REQUIRE(o.v0, "null start vector");
     n_nodes = int64_t(grid[0]) * grid[1] * grid[2];
@@ -428,6 +501,20 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     }
     b0_d.alloc(n_nodes * 8);
     TBH_HIP(hipMemcpy(b0_d.p, b0.data(), n_nodes * 8, hipMemcpyHostToDevice));
+    // donor count and sublattice occupation per node (the learned start's inputs)
+    {
+        std::vector<float> dm(size_t(n_nodes), 0.f), mk(size_t(2 * n_nodes), 0.f);
+        for (int d = 0; d < o.n_donors; ++d) dm[size_t(node_of(o.donor_atoms[d]))] += 1.f;
+        for (int64_t a = 0; a < h->n; ++a) {
+            const int32_t* q = &h->pos_h[3 * a];
+            const bool bsub = (q[0] + q[1] + q[2]) % 4 == 3;
+            mk[size_t((bsub ? n_nodes : 0) + node_of(a))] = 1.f;
+        }
+        dmap_d.alloc(size_t(n_nodes) * 4);
+        mask_d.alloc(size_t(2 * n_nodes) * 4);
+        TBH_HIP(hipMemcpy(dmap_d.p, dm.data(), dm.size() * 4, hipMemcpyHostToDevice));
+        TBH_HIP(hipMemcpy(mask_d.p, mk.data(), mk.size() * 4, hipMemcpyHostToDevice));
+    }
     U.alloc(n_nodes * 8);
     phi.alloc(n_nodes * 8);
     b.alloc(n_nodes * 8);
@@ -446,17 +533,84 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     } else {
         TBH_HIP(hipMemcpy(v0.p, o.v0, ns * 8, hipMemcpyHostToDevice));
     }
-    part.alloc(size_t(std::max<int64_t>(2 * 4096, int64_t(o.n_cand) * 4096)) * 8);
-    occ.alloc(size_t(o.n_cand) * 8);
-    q.alloc(size_t(o.n_cand) * 8);
+    const int64_t nst = o.eig_mode == 1 ? o.block : o.n_cand;
+    part.alloc(size_t(std::max<int64_t>(2 * 4096, nst * 4096)) * 8);
+    occ.alloc(size_t(nst) * 8);
+    q.alloc(size_t(nst) * 8);
     out.alloc(8 * 8);
     n_atoms_d.alloc(h->n * 8);
     (void)st;
 }
 
+void Scf::compute_ubare() {
+    if (have_ubare) return;
+    hipStream_t st = h->ctx->stream;
+    ubare_d.alloc(size_t(n_nodes) * 8);
+    DevBuf phib;
+    phib.alloc(size_t(n_nodes) * 8);
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, b0_d.as<double>(), 0.0,
+                       phib.as<double>());
+    int it = 0;
+    double rr = 0.0;
+    poisson_cg(st, pw, grid, opt.h_nm, b0_d.as<double>(), phib.as<double>(), 1e-12, 100000, &it, &rr);
+    TBH_REQUIRE(rr <= 1e-10, "bare-donor Poisson solve did not converge");
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, phib.as<double>(), -1.0,
+                       ubare_d.as<double>());
+    TBH_HIP(hipStreamSynchronize(st));
+    have_ubare = true;
+}
+
+void Scf::set_start(const tbh_scf_start& sp) {
+    hipStream_t st = h->ctx->stream;
+    TBH_REQUIRE(sp.kind >= 0 && sp.kind <= 2, "start kind must be 0 (zero), 1 (mean) or 2 (learned)");
+    TBH_REQUIRE(sp.first_res_limit >= 0, "first_res_limit must be >= 0");
+    if (sp.kind == 0) {
+        set_potential(nullptr);
+    } else {
+        TBH_REQUIRE(sp.mean_dev, "mean and learned starts need the mean map");
+        compute_ubare();
+        const int64_t gn = grid_for(n_nodes);
+        if (sp.kind == 1) {
+            hipLaunchKernelGGL(k_start_combine, dim3(gn), dim3(TPB), 0, st, n_nodes, ubare_d.as<double>(),
+                               sp.mean_dev, (const float*)nullptr, 0.0, U.as<double>());
+        } else {
+            TBH_REQUIRE(sp.net, "the learned start needs a network");
+            Net& net = *reinterpret_cast<Net*>(sp.net);
+            TBH_REQUIRE(net.CI == 4 && net.g[0] == grid[0] && net.g[1] == grid[1] && net.g[2] == grid[2],
+                        "the network needs 4 input channels on the loop's grid");
+            TBH_REQUIRE(sp.feat_scale > 0, "feat_scale must be positive");
+            TBH_REQUIRE(!sp.symmetrize || grid[0] == grid[1], "symmetrizing over the point operations needs nx = ny");
+            xin_d.alloc(size_t(4 * n_nodes) * 4);
+            xop_d.alloc(size_t(4 * n_nodes) * 4);
+            yop_d.alloc(size_t(2 * n_nodes) * 4);
+            acc_d.alloc(size_t(n_nodes) * 4);
+            hipLaunchKernelGGL(k_start_inputs, dim3(gn), dim3(TPB), 0, st, n_nodes, dmap_d.as<float>(),
+                               mask_d.as<float>(), ubare_d.as<double>(), 1.0 / sp.feat_scale, xin_d.as<float>());
+            const int nops = sp.symmetrize ? 4 : 1;
+            float* y = yop_d.as<float>();
+            float* yb = y + n_nodes;
+            for (int op = 0; op < nops; ++op) {
+                hipLaunchKernelGGL(k_point_op, dim3(grid_for(4 * n_nodes)), dim3(TPB), 0, st, n_nodes, 4, grid[0],
+                                   grid[1], op, xin_d.as<float>(), xop_d.as<float>());
+                net.forward(xop_d.as<float>(), y);
+                hipLaunchKernelGGL(k_point_op, dim3(gn), dim3(TPB), 0, st, n_nodes, 1, grid[0], grid[1], op, y, yb);
+                hipLaunchKernelGGL(k_accum, dim3(gn), dim3(TPB), 0, st, n_nodes, yb, acc_d.as<float>(), op == 0 ? 1 : 0);
+            }
+            hipLaunchKernelGGL(k_start_combine, dim3(gn), dim3(TPB), 0, st, n_nodes, ubare_d.as<double>(),
+                               sp.mean_dev, acc_d.as<float>(), sp.scale / nops, U.as<double>());
+        }
+        TBH_HIP(hipGetLastError());
+        set_potential(U.as<double>());
+    }
+    start_kind = sp.kind;
+    first_res_limit = sp.first_res_limit;
+    since_start = 0;
+    grow = 0;
+}
+
 void Scf::set_potential(const double* Ud) {
     hipStream_t st = h->ctx->stream;
-    if (Ud)
+    if (Ud && Ud != U.as<double>())
         TBH_HIP(hipMemcpyAsync(U.p, Ud, n_nodes * 8, hipMemcpyDeviceToDevice, st));
     else
         hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), 0.0,
@@ -465,6 +619,12 @@ void Scf::set_potential(const double* Ud) {
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), -1.0,
                        phi.as<double>());
     TBH_HIP(hipGetLastError());
+    // a new start: the previous step's filled states no longer locate the band edge
+    have_prev = false;
+    last_res = 0.0;
+    start_kind = 0;
+    since_start = 0;
+    grow = 0;
 }
 
 void Scf::step(tbh_scf_report& rep) {
@@ -478,36 +638,78 @@ void Scf::step(tbh_scf_report& rep) {
     h->pot_d.alloc(size_t(h->n) * 8);
     TBH_HIP(hipMemcpyAsync(h->pot_d.p, Ua.p, h->n * 8, hipMemcpyDeviceToDevice, st));
     h->has_pot = true;
-    // Lanczos target: bulk CBM shifted by the deepest potential
-    hipLaunchKernelGGL(k_min, dim3(gn), dim3(TPB), 0, st, n_nodes, U.as<double>(), pt);
+    // band-edge estimates: bulk edges shifted by the extreme potential
+    hipLaunchKernelGGL(k_minmax, dim3(gn), dim3(TPB), 0, st, n_nodes, U.as<double>(), pt);
     hipLaunchKernelGGL(k_mix_reduce, dim3(1), dim3(TPB), 0, st, pt, gn, out.as<double>() + 4);
     double mm[2];
     TBH_HIP(hipMemcpyAsync(mm, out.as<double>() + 4, 16, hipMemcpyDeviceToHost, st));
     TBH_HIP(hipStreamSynchronize(st));
-    // target: just below the lowest filled state of the previous step; on the
-    // first step (or if none was filled) the bulk CBM shifted by min U
-    const double sigma = have_prev ? prev_emin - 0.05 : opt.e_cbm + mm[1];
-    if (!lz) lz = std::make_shared<LzWork>();
-    int steps = 0, brk = 0;
-    lanczos_recurrence(*h, *lz, opt.lanczos_iter, true, v0.as<double>(), nullptr, nullptr, &steps, &brk, nullptr);
-    const int ncand = std::min(opt.n_cand, steps);
-    ritz_pairs(*h, *lz, steps, sigma, ncand, ritz);
+    const double u_max = mm[0], u_min = mm[1];
+    int steps = 0, ncand = 0;
+    const double* Ys = nullptr;
+    const double* res4 = nullptr;
+    double res_tol_fill = opt.res_tol;
+    double sigma = 0.0;
+    if (opt.eig_mode == 0) {
+        // target: just below the lowest filled state of the previous step; on
+        // the first step (or if none was filled) the bulk CBM shifted by min U
+        sigma = have_prev ? prev_emin - 0.05 : opt.e_cbm + u_min;
+        if (!lz) lz = std::make_shared<LzWork>();
+        int brk = 0;
+        lanczos_recurrence(*h, *lz, opt.lanczos_iter, true, v0.as<double>(), nullptr, nullptr, &steps, &brk,
+                           nullptr);
+        ncand = std::min(opt.n_cand, steps);
+        ritz_pairs(*h, *lz, steps, sigma, ncand, ritz);
+        Ys = ritz.Y.as<double>();
+        res4 = ritz.res.as<double>();
+    } else {
+        if (!fs) {
+            fs = std::make_shared<FsWork>();
+            blw = std::make_shared<BlWork>();
+        }
+        fs->ensure(h->dim, opt.block);
+        if (!have_bounds) {
+            spectral_bounds(*h, &emin_b, &emax_b);
+            // room for the potential to change over the loop
+            emin_b -= 2.0;
+            emax_b += 2.0;
+            have_bounds = true;
+        }
+        const double e_cb = have_prev ? prev_emin : opt.e_cbm + u_min;
+        const double e_vb = opt.e_vbm + u_max;
+        FsSolve so;
+        so.s = e_vb + 0.75 * (e_cb - e_vb);
+        so.emin = emin_b;
+        so.emax = emax_b;
+        so.degree = opt.filter_degree;
+        so.degree_cold = opt.filter_degree_cold;
+        so.min_iter = 1;
+        so.max_iter = opt.filter_max_iter;
+        so.k = opt.k_states;
+        so.res_tol = fs_warm ? std::max(opt.res_tol, 0.1 * last_res) : opt.res_tol;
+        sigma = so.s;
+        steps = filtered_solve(*h, *blw, *fs, so, fs_warm, nullptr, nullptr);
+        fs_warm = true;
+        ncand = opt.block;
+        Ys = fs->states.as<double>();
+        res4 = fs->res4.as<double>();
+        res_tol_fill = INFINITY;   // every state of the block takes part in the filling
+    }
     const auto t1 = std::chrono::steady_clock::now();
     // charge
     const size_t ns = size_t(h->dim) * (h->cplx_h ? 2 : 1);
     const int cs = h->cplx_h ? 2 : 1;
     dim3 g2(ga, ncand);
-    hipLaunchKernelGGL(k_state_pot, g2, dim3(TPB), 0, st, ritz.Y.as<double>(), int64_t(ns), h->n_o, cs, h->n,
-                       Ua.as<double>(), pt);
+    hipLaunchKernelGGL(k_state_pot, g2, dim3(TPB), 0, st, Ys, int64_t(ns), h->n_o, cs, h->n, Ua.as<double>(), pt);
     hipLaunchKernelGGL(k_reduce_rows, dim3(ncand), dim3(TPB), 0, st, pt, ga, q.as<double>());
     const double kT = KB_EV * opt.T_K;
     const int use_fixed = std::isnan(opt.fermi_fixed) ? 0 : 1;
-    hipLaunchKernelGGL(k_fermi, dim3(1), dim3(64), 0, st, ncand, ritz.res.as<double>(), q.as<double>(),
-                       opt.res_tol, opt.sigma_mid, double(opt.n_donors), kT, use_fixed ? opt.fermi_fixed : 0.0,
-                       use_fixed, occ.as<double>(), out.as<double>());
+    hipLaunchKernelGGL(k_fermi, dim3(1), dim3(64), 0, st, ncand, res4, q.as<double>(), res_tol_fill,
+                       opt.sigma_mid, double(opt.n_donors), kT, use_fixed ? opt.fermi_fixed : 0.0, use_fixed,
+                       occ.as<double>(), out.as<double>());
     const double scale = 1.0 / (opt.h_nm * opt.h_nm * opt.h_nm * EPS0_E_PER_V_NM * opt.eps_r);
     TBH_HIP(hipMemcpyAsync(b.p, b0_d.p, n_nodes * 8, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_density_rhs, dim3(ga), dim3(TPB), 0, st, ritz.Y.as<double>(), int64_t(ns), ncand,
+    hipLaunchKernelGGL(k_density_rhs, dim3(ga), dim3(TPB), 0, st, Ys, int64_t(ns), ncand,
                        h->n_o, cs, h->n, occ.as<double>(), node_d.as<int64_t>(), scale, b.as<double>(),
                        n_atoms_d.as<double>());
     // Poisson (phi holds the previous solution as the guess)
@@ -526,6 +728,22 @@ void Scf::step(tbh_scf_report& rep) {
     ++iterations;
     have_prev = o[1] > 0;
     prev_emin = o[6];
+    last_res = o[4];
+    // fallback: a start that is not the zero start is abandoned when the loop
+    // diverges from it (non-finite residual, three rises in a row) or its first
+    // residual exceeds the limit
+    rep.fell_back = 0;
+    ++since_start;
+    if (start_kind != 0 && !(o[4] < opt.tol_eV)) {
+        grow = (since_start > 1 && o[4] > prev_res) ? grow + 1 : 0;
+        const bool bad = !std::isfinite(o[4]) || grow >= 3 ||
+                         (since_start == 1 && first_res_limit > 0 && o[4] > first_res_limit);
+        if (bad) {
+            set_potential(nullptr);
+            rep.fell_back = 1;
+        }
+    }
+    prev_res = o[4];
     rep.iterations = iterations;
     rep.residual = o[4];
     rep.converged = o[4] < opt.tol_eV;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
 #include <memory>
 #include <cstdint>
@@ -147,6 +148,8 @@ void pack_atom_major(const HostModel& m, int64_t stride, float* dst);
 // ---------------------------------------------------------------------------
 struct Ctx;
 struct LzWork;
+struct BlWork;
+struct FsWork;
 struct Ham {
     Ctx* ctx = nullptr;
     int64_t n = 0, dim = 0;
@@ -162,6 +165,8 @@ struct Ham {
     std::vector<int8_t> wrap_h;
     std::vector<int32_t> pos_h;   // [n][3] positions (a/4 units)
     std::shared_ptr<LzWork> lz;   // Lanczos workspace kept between calls
+    std::shared_ptr<BlWork> bl;   // block Lanczos workspace kept between calls
+    std::shared_ptr<FsWork> fs;   // filtered-subspace block kept between calls (warm starts)
     // The packed stream, nbr_d, pot_d and every vector inside the library
     // (Lanczos basis, SCF states) use the stream order; the caller's atom
     // order is restored at the boundary (tbh_apply_h*, start vectors, Ritz
@@ -171,6 +176,7 @@ struct Ham {
     DevBuf perm_d, xs, ys;        // device perm; staging vectors of tbh_apply_h*
     int64_t caller(int64_t k) const { return permuted ? perm_h[size_t(k)] : k; }
     int64_t hx_bytes() const;
+    std::atomic<int> refs{1};
 };
 
 // ---------------------------------------------------------------------------
@@ -190,7 +196,17 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     DevBuf partial, scal;  // reduction scratch
+    std::atomic<int> refs{1};   // the caller's handle plus one per object built on it
 };
+
+// Reference counts: a ham, net or batch keeps its context alive, and an SCF
+// loop or batch keeps its hams alive, until it is destroyed itself, so the
+// handles can be destroyed in any order.  release() frees the object (after
+// synchronising its stream) when the last reference goes.
+void retain(Ctx* c);
+void release(Ctx* c);
+void retain(Ham* h);
+void release(Ham* h);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (hx.hip)
@@ -217,6 +233,7 @@ void hx_launch(const Layout& lay, bool f64, const HxArgs& a, hipStream_t s);
 
 // error slot shared by every C ABI translation unit (thread-local)
 void set_error(const std::string& msg);
+
 
 // Run f, translating exceptions into a status code and the error message.
 template <typename F>

@@ -1,29 +1,32 @@
 """Learned start potential for the self-consistent loop.
 
-    python -m paper_1003_4570_amd.surrogate gen   --out DIR --seeds 0:96
-    python -m paper_1003_4570_amd.surrogate pack  --out DATA.npz DIR [DIR ...]
-    python -m paper_1003_4570_amd.surrogate train --data DIR --out W.npz [--target U|E]
-    python -m paper_1003_4570_amd.surrogate eval  --weights W.npz --seeds 1000:1016
+    python -m paper_1003_4570_amd.surrogate --geometry c5 gen   --out DIR --seeds 0:100
+    python -m paper_1003_4570_amd.surrogate --geometry c5 pack  --out DATA.npz DIR [DIR ...]
+    python -m paper_1003_4570_amd.surrogate --geometry c5 train --data DATA.npz --out W.npz
+    python -m paper_1003_4570_amd.surrogate --geometry c5 eval  --weights W.npz --seeds 1000:1016
 
 The self-consistent Schrodinger-Poisson loop (Sec. III-A) is run by the
-library (tbh_scf_*); this module drives it: it generates converged
-potentials with the plain method (zero start, linear mixing), trains the
+library (tbh_scf_*), and so is every step of the learned start: building the
+network's input maps, the forward passes, the average over the slab's point
+operations, forming U0 and the fallback to the zero start
+(tbh_scf_set_start).  This module orchestrates: it generates converged
+solutions with the plain method (zero start, linear mixing), trains the
 convolutional surrogate on them with the library's device kernels
 (tbh_net_*), and compares SCF time-to-converge from the zero start, the
 training-mean start and the learned start on held-out donor layouts.
 
 The network (by default four layers; deeper dilation lists are supported)
-sees four maps on the a/4 grid: the donor count, the two
-sublattice occupation masks (a diamond lattice fills only one node in eight,
-and which nodes it fills is not invariant under a one-node shift, so without
-them a convolution cannot tell an atom site from an empty node) and the
-electron potential energy of the bare donor charge (the Poisson solution of
-the donors alone in the dielectric, divided by a fixed scale), which carries
-the long-range part the network's finite receptive field cannot reach.  The
-zero start stays the fallback: a learned start is abandoned (and the loop
-restarted from zero) when the potential turns non-finite, the residual grows
-three steps in a row, or the first residual exceeds ten times the zero
-start's.
+sees four maps on the a/4 grid: the donor count, the two sublattice
+occupation masks (a diamond lattice fills only one node in eight, and which
+nodes it fills is not invariant under a one-node shift, so without them a
+convolution cannot tell an atom site from an empty node) and the electron
+potential energy of the bare donor charge (the Poisson solution of the donors
+alone in the dielectric, divided by a fixed scale), which carries the
+long-range part the network's finite receptive field cannot reach.  Its
+target is the electron part E = U* - U_bare of the converged potential.  The
+zero start stays the fallback: a start is abandoned (and the loop restarted
+from zero) when the residual turns non-finite, grows three steps in a row,
+or the first residual exceeds ten times the zero start's.
 """
 from __future__ import annotations
 
@@ -45,8 +48,19 @@ import workloads as W  # noqa: E402
 
 N_IN = 4   # input maps: donor count, A and B sublattice masks, bare-donor potential
 
-SCF_DEFAULTS = dict(mix_alpha=0.05, tol_eV=1e-4, n_cand=64, lanczos_iter=800, res_tol=1e-4, T_K=4.0,
-                    eps_r=11.7)
+# The loop's settings per geometry.  The study slab (3x3x8 cells, 576 atoms)
+# keeps the Lanczos eigen-solve (64 candidates of 800 CGS2 steps); the
+# 8x8x60-cell delta-doped slab (30,720 atoms) uses the filtered block solver
+# (a block of 64 states, folded Chebyshev filters, warm-started every step).
+GEOMETRIES = {
+    "study": dict(problem=W.study_slab,
+                  scf=dict(mix_alpha=0.05, tol_eV=1e-4, n_cand=64, lanczos_iter=800, res_tol=1e-4, T_K=4.0,
+                           eps_r=11.7)),
+    "c5": dict(problem=W.c5_slab,
+               scf=dict(mix_alpha=0.05, tol_eV=1e-4, res_tol=1e-4, T_K=4.0, eps_r=11.7, eig_mode=1, block=64,
+                        filter_degree=20, filter_degree_cold=80, filter_max_iter=60, k_states=40)),
+}
+SCF_DEFAULTS = GEOMETRIES["study"]["scf"]
 
 
 def _seeds(spec):
@@ -54,22 +68,52 @@ def _seeds(spec):
     return list(range(int(a), int(b)))
 
 
-class Study:
-    """One Hamiltonian shared by every donor layout of the study slab."""
+class Start:
+    """A trained start: the network (library handle), the training mean of
+    the target on the device, its scale, the input scale and the target kind
+    ("E": U* minus the bare-donor potential; "U": U* itself)."""
 
-    def __init__(self, ctx=None, **scf_kw):
+    def __init__(self, study, weights):
+        import torch
+        wz = np.load(weights)
+        nz, ny, nx = wz["Tbar"].shape
+        dil = tuple(int(d) for d in wz["dilations"]) if "dilations" in wz.files else (1, 2, 4, 1)
+        self.net = tbh.Net(study.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dil)
+        self.net.set_params(wz["params"])
+        self.Tbar = torch.from_numpy(np.asarray(wz["Tbar"], dtype=np.float32)).cuda()
+        self.scale = float(wz["scale"])
+        self.feat_scale = float(wz["feat_scale"])
+        self.target = str(wz["target"])
+        self.train_seeds = set(int(v) for v in wz["train_seeds"])
+        if self.target != "E":
+            raise ValueError("the device start builds U_bare + mean + scale * net: weights with target E")
+
+
+class Study:
+    """One Hamiltonian shared by every donor layout of a slab geometry (the
+    layouts differ in their donor sites and Lanczos start vector only)."""
+
+    def __init__(self, ctx=None, geometry="study", **scf_kw):
         import torch
         self.ctx = ctx or tbh.Context(0)
-        p0 = W.study_slab(0)
+        self.geometry = geometry
+        G = GEOMETRIES[geometry]
+        self.problem = G["problem"]
+        p0 = self.problem(0)
         self.grid = p0.extra["grid"]
         self.gap = p0.extra["gap"]
-        self.ham = tbh.build_hamiltonian(self.ctx, **tbh.problem_args(p0, prec="f32", keep_f64=True))
-        self.kw = dict(SCF_DEFAULTS)
+        self.pos_q = p0.pos_q
+        self.kw = dict(G["scf"])
+        if self.kw.get("eig_mode", 0) == 1:
+            self.kw["e_vbm"] = self.gap["vbm"]
         self.kw.update(scf_kw)
+        multi = self.kw.get("eig_mode", 0) == 1
+        self.ham = tbh.build_hamiltonian(self.ctx, **tbh.problem_args(p0, prec="f32", keep_f64=True,
+                                                                      multi_vector=multi))
         self.torch = torch
 
     def scf(self, seed):
-        p = W.study_slab(seed)
+        p = self.problem(seed)
         s = tbh.SCF(self.ham, self.grid, p.extra["donor_atoms"], p.v0, self.gap["mid"], self.gap["cbm"],
                     W.H_GRID_NM, **self.kw)
         return s, p
@@ -87,80 +131,83 @@ class Study:
             raise RuntimeError(f"bare-donor Poisson solve did not converge (relative residual {rel})")
         return -phi
 
+    def electron_potential(self, n_atoms):
+        """Potential energy of the electrons (eV, device FP64 map) for the
+        electrons per atom n (device FP64, caller order): with rho = -e n / h^3
+        on the atom nodes, U_e = -phi(rho); U* = U_bare + U_e at the fixed point."""
+        torch = self.torch
+        nx, ny, nz = self.grid
+        q = torch.from_numpy(self.pos_q.astype(np.int64)).cuda()
+        nmap = torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda")
+        nmap.index_put_((q[:, 2], q[:, 1], q[:, 0]), n_atoms.double(), accumulate=True)
+        phi, _, rel = tbh.poisson_solve(self.ctx, self.grid, W.H_GRID_NM, self.kw["eps_r"],
+                                        (nmap / W.H_GRID_NM ** 3).contiguous(), rel_tol=1e-12)
+        if not rel <= 1e-10:
+            raise RuntimeError(f"electron Poisson solve did not converge (relative residual {rel})")
+        return phi
+
     def inputs(self, dmap, feat_scale):
-        """The network's input maps, float32 [4, nz, ny, nx] on the device."""
+        """The network's input maps, float32 [4, nz, ny, nx] on the device
+        (training; at inference the library builds the same maps itself)."""
         torch = self.torch
         if not hasattr(self, "_masks"):
-            self._masks = torch.from_numpy(W.sublattice_masks(W.study_slab(0).pos_q, self.grid)).cuda()
+            self._masks = torch.from_numpy(W.sublattice_masks(self.pos_q, self.grid)).cuda()
         d = torch.from_numpy(np.asarray(dmap, dtype=np.float32)).cuda()
         ub = (self.bare_potential(dmap) / feat_scale).float()
         return torch.stack([d, self._masks[0], self._masks[1], ub]).contiguous()
 
-    def surrogate(self, weights, symmetrize_output=True):
-        """Load trained weights; returns start(dmap) -> device FP64 [nz, ny, nx].
-        With symmetrize_output the network's output is averaged over the
-        in-plane point operations of the slab (point_ops): each is applied
-        to the input maps, the output mapped back, and the four averaged."""
-        wz = np.load(weights)
-        nz, ny, nx = wz["Tbar"].shape
-        dil = tuple(int(d) for d in wz["dilations"]) if "dilations" in wz.files else (1, 2, 4, 1)
-        net = tbh.Net(self.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dil)
-        net.set_params(wz["params"])
-        Tbar = self.torch.from_numpy(wz["Tbar"]).cuda()
-        scale, fs, target = float(wz["scale"]), float(wz["feat_scale"]), str(wz["target"])
+    def surrogate(self, weights):
+        return Start(self, weights)
 
-        def start(dmap):
-            x = self.inputs(dmap, fs)
-            if symmetrize_output:
-                y = sum(inv(net.forward(op(x).contiguous())) for op, inv in point_ops()) / 4.0
-            else:
-                y = net.forward(x)
-            u = Tbar + scale * y.double()
-            return u + self.bare_potential(dmap) if target == "E" else u
-        start.Tbar = Tbar
-        start.target = target
-        start.train_seeds = set(int(v) for v in wz["train_seeds"])
-        return start
-
-    def run(self, seed, U0=None, max_iter=400, first_res_ref=None, fallback=False):
-        """SCF from U0 (device [nz,ny,nx] FP64 or None = zero).  Returns the
-        record (iterations, seconds, residuals, converged, fell_back, U)."""
+    def run(self, seed, start=None, max_iter=400, first_res_limit=0.0, mean_only=False, fixed_start=None):
+        """SCF of one layout from the zero start (start None), the mean start
+        (start and mean_only) or the learned start (start), the start built
+        by the library (tbh_scf_set_start, its time included), or from an
+        explicit FP32 device map added to U_bare as the mean start
+        (fixed_start: a test of the fallback).  Returns the record
+        (iterations, seconds, residuals, converged, fell_back, U, U0)."""
         torch = self.torch
         s, p = self.scf(seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s.set_potential(U0)
-        res, fell, grow = [], False, 0
+        if fixed_start is not None:
+            s.set_start("mean", mean=fixed_start, first_res_limit=first_res_limit)
+        elif start is None:
+            s.set_start("zero")
+        elif mean_only:
+            s.set_start("mean", mean=start.Tbar, first_res_limit=first_res_limit)
+        else:
+            s.set_start("learned", net=start.net, mean=start.Tbar, scale=start.scale,
+                        feat_scale=start.feat_scale, symmetrize=True, first_res_limit=first_res_limit)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter() - t0
+        U0 = s.potential()
+        t1 = time.perf_counter()
+        res, fell = [], False
         it = 0
+        r = None
         while it < max_iter:
             r = s.step()
             it += 1
             res.append(r["residual"])
+            fell = fell or bool(r["fell_back"])
             if r["converged"]:
                 break
-            if fallback and not fell:
-                bad = not np.isfinite(r["residual"])
-                if len(res) >= 2 and res[-1] > res[-2]:
-                    grow += 1
-                else:
-                    grow = 0
-                if len(res) == 1 and first_res_ref is not None and res[0] > 10 * first_res_ref:
-                    bad = True
-                if bad or grow >= 3:
-                    fell = True
-                    s.set_potential(None)
-                    res.append(float("nan"))
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt = t_start + (time.perf_counter() - t1)
         U = s.potential()
+        n = s.density() if it else None
         s.close()
-        return dict(seed=seed, iterations=it, seconds=dt, residuals=res, converged=bool(res and res[-1] < self.kw["tol_eV"]),
-                    fell_back=fell, U=U)
+        return dict(seed=seed, iterations=it, seconds=dt, start_seconds=t_start, residuals=res,
+                    converged=bool(r is not None and r["converged"]), fell_back=fell, U=U, U0=U0, n=n)
 
 
-def generate(out_dir, seeds, max_iter=400, budget_s=None):
+def generate(out_dir, seeds, max_iter=400, budget_s=None, geometry="study"):
+    """Plain-method (zero start) SCF runs; per converged layout the electrons
+    per atom (float32, caller order; the converged potential is U_bare plus
+    their Poisson potential), iterations and seconds."""
     os.makedirs(out_dir, exist_ok=True)
-    st = Study()
+    st = Study(geometry=geometry)
     t0 = time.perf_counter()
     for sd in seeds:
         if budget_s is not None and time.perf_counter() - t0 > budget_s:
@@ -169,56 +216,48 @@ def generate(out_dir, seeds, max_iter=400, budget_s=None):
         if os.path.exists(os.path.join(out_dir, f"layout_{sd:05d}.npz")):
             continue
         rec = st.run(sd, None, max_iter)
-        p = W.study_slab(sd)
-        np.savez(os.path.join(out_dir, f"layout_{sd:05d}.npz"), donor_map=st.donor_map(p),
-                 U=rec["U"].cpu().numpy(), iterations=rec["iterations"], seconds=rec["seconds"],
-                 converged=rec["converged"])
+        np.savez(os.path.join(out_dir, f"layout_{sd:05d}.npz"), n=rec["n"].float().cpu().numpy(),
+                 iterations=rec["iterations"], seconds=rec["seconds"], converged=rec["converged"])
         print(json.dumps(dict(seed=sd, iterations=rec["iterations"], seconds=round(rec["seconds"], 3),
                               converged=rec["converged"])), flush=True)
 
 
 def pack(out_path, sources):
-    """Merge converged layouts (per-layout directories written by generate()
-    or packed files) into one compressed .npz: seeds, donor_map (int8),
-    U (FP32), iterations, seconds.  A seed seen twice keeps its last copy."""
+    """Merge converged layouts (per-layout files written by generate() or
+    packed files) into one compressed .npz: seeds, n (electrons per atom,
+    float32 [layouts, atoms]), iterations, seconds.  A seed seen twice keeps
+    its last copy."""
     acc = {}
     for src in sources:
         if os.path.isdir(src):
-            for f in sorted(os.listdir(src)):
-                if not (f.startswith("layout_") and f.endswith(".npz")):
+            for fn in sorted(os.listdir(src)):
+                if not (fn.startswith("layout_") and fn.endswith(".npz")):
                     continue
-                d = np.load(os.path.join(src, f))
+                d = np.load(os.path.join(src, fn))
                 if bool(d["converged"]):
-                    acc[int(f[7:12])] = (d["donor_map"].astype(np.int8), d["U"].astype(np.float32),
-                                         int(d["iterations"]), float(d["seconds"]))
+                    acc[int(fn[7:12])] = (d["n"].astype(np.float32), int(d["iterations"]), float(d["seconds"]))
         else:
             d = np.load(src)
             for i, sd in enumerate(d["seeds"]):
-                acc[int(sd)] = (d["donor_map"][i], d["U"][i], int(d["iterations"][i]), float(d["seconds"][i]))
+                acc[int(sd)] = (d["n"][i], int(d["iterations"][i]), float(d["seconds"][i]))
     keys = sorted(acc)
-    np.savez_compressed(out_path, seeds=np.array(keys), donor_map=np.stack([acc[k][0] for k in keys]),
-                        U=np.stack([acc[k][1] for k in keys]), iterations=np.array([acc[k][2] for k in keys]),
-                        seconds=np.array([acc[k][3] for k in keys]))
+    np.savez_compressed(out_path, seeds=np.array(keys), n=np.stack([acc[k][0] for k in keys]),
+                        iterations=np.array([acc[k][1] for k in keys]),
+                        seconds=np.array([acc[k][2] for k in keys]))
     return len(keys)
 
 
-def load_dataset(data_dir):
-    """Converged layouts from a directory of per-layout files, or from one
-    packed .npz (arrays seeds, donor_map [n, nz, ny, nx], U [n, nz, ny, nx])."""
-    if os.path.isfile(data_dir):
-        d = np.load(data_dir)
-        return d["donor_map"].astype(np.float32), d["U"].astype(np.float64), [int(v) for v in d["seeds"]]
-    xs, us, seeds = [], [], []
-    for f in sorted(os.listdir(data_dir)):
-        if not f.startswith("layout_") or not f.endswith(".npz"):
-            continue
-        d = np.load(os.path.join(data_dir, f))
-        if not bool(d["converged"]):
-            continue
-        xs.append(d["donor_map"].astype(np.float32))
-        us.append(d["U"].astype(np.float64))
-        seeds.append(int(f[7:12]))
-    return np.stack(xs), np.stack(us), seeds
+def load_dataset(path, study):
+    """Donor maps, bare-donor potentials and electron potentials (targets) of
+    the packed layouts: float32 donor maps [n, nz, ny, nx], device FP64 maps,
+    seeds."""
+    torch = study.torch
+    d = np.load(path)
+    seeds = [int(v) for v in d["seeds"]]
+    X = np.stack([study.donor_map(study.problem(sd)) for sd in seeds])
+    Ub = torch.stack([study.bare_potential(x) for x in X])
+    E = torch.stack([study.electron_potential(torch.from_numpy(n).cuda()) for n in d["n"]])
+    return X, Ub, E, seeds
 
 
 def lattice_shifts(grid):
@@ -258,63 +297,60 @@ def symmetrize(a, grid):
     return np.mean([np.roll(a, (sy, sx), axis=(-2, -1)) for sx, sy in lattice_shifts(grid)], axis=0)
 
 
-def near_plane_weights(grid, donor_z, near_weight, half_width=3):
+def near_plane_weights(study, donor_z, near_weight, half_width=3):
     """Loss weights 1 + near_weight on atom nodes within half_width grid
     planes of the donor plane (where the start error is largest), 1
     elsewhere; float32 [nz, ny, nx]."""
-    nx, ny, nz = grid
-    m = W.sublattice_masks(W.study_slab(0).pos_q, grid).sum(axis=0) > 0
+    nx, ny, nz = study.grid
+    m = W.sublattice_masks(study.pos_q, study.grid).sum(axis=0) > 0
     z = np.arange(nz)[:, None, None]
     return (1.0 + near_weight * (m & (np.abs(z - donor_z) <= half_width))).astype(np.float32)
 
 
-def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", n_val=0, ctx=None,
-          dilations=(1, 2, 4, 1), near_weight=0.0):
-    """Fit the network to converged potentials.  target "U": the network
-    gives U* directly; "E": it gives U* minus the bare-donor potential (the
-    electron part), added back at inference.  The targets are taken relative
-    to their training mean averaged over the lattice translations (an exact
-    symmetry of the donor ensemble), and every epoch shows each layout under
-    a random lattice translation.  near_weight > 0 weights the loss on the
-    atoms next to the donor plane (near_plane_weights).  The last n_val
-    layouts are held out and the max-norm start error on them reported.  The
-    learning rate follows a cosine decay from lr to zero."""
+def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=None, dilations=(1, 2, 4, 1),
+          near_weight=0.0, geometry="study", time_budget=None):
+    """Fit the network to the electron part E = U* - U_bare of converged
+    potentials (added back to the exact U_bare at inference).  The targets
+    are taken relative to their training mean averaged over the lattice
+    translations (an exact symmetry of the donor ensemble), and every epoch
+    shows each layout under a random lattice translation.  near_weight > 0
+    weights the loss on the atoms next to the donor plane.  The last n_val
+    layouts are held out and their max-norm start error reported.  The
+    learning rate follows a cosine decay from lr to zero (over epochs, or
+    over time_budget seconds when given)."""
     import torch
-    st = Study(ctx)
-    X, U, seeds = load_dataset(data_dir)
+    st = Study(ctx, geometry=geometry)
+    X, Ub, E, seeds = load_dataset(data, st)
     grid = st.grid
-    Ub = np.stack([st.bare_potential(x).cpu().numpy() for x in X])
-    feat_scale = float(np.std(Ub))
-    Y = U - Ub if target == "E" else U
+    feat_scale = float(Ub.std())
     ntr = len(X) - n_val
-    Tbar = symmetrize(Y[:ntr].mean(axis=0), grid)
-    scale = float((Y[:ntr] - Tbar).std())
-    T = ((Y - Tbar) / scale).astype(np.float32)
+    Tbar = symmetrize(E[:ntr].mean(dim=0).cpu().numpy(), grid)
+    Tbar_d = torch.from_numpy(Tbar).cuda()
+    scale = float((E[:ntr] - Tbar_d).std())
+    T = ((E - Tbar_d) / scale).float()
     nz, ny, nx = X.shape[1:]
     net = tbh.Net(st.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dilations)
     net.set_params(W.init_surrogate_weights(seed, in_channels=N_IN, n_layers=len(dilations)))
     if near_weight > 0:
         donor_z = int(np.flatnonzero(X.sum(axis=(0, 2, 3)))[0])
-        net.set_loss_weights(torch.from_numpy(near_plane_weights(grid, donor_z, near_weight)).cuda())
+        net.set_loss_weights(torch.from_numpy(near_plane_weights(st, donor_z, near_weight)).cuda())
     Xd = [st.inputs(x, feat_scale) for x in X]
-    Td = [torch.from_numpy(t).cuda() for t in T]
+    Td = [t.contiguous() for t in T]
     shifts = lattice_shifts(grid)
     rng = np.random.default_rng(seed)
-    Tbar_d = torch.from_numpy(Tbar).cuda()
 
     def val_errors():
         e = []
         for i in range(ntr, len(X)):
             u = Tbar_d + scale * net.forward(Xd[i]).double()
-            if target == "E":
-                u = u + torch.from_numpy(Ub[i]).cuda()
-            e.append(float((u - torch.from_numpy(U[i]).cuda()).abs().max()))
+            e.append(float((u - E[i]).abs().max()))
         return e
 
     hist = []
     t0 = time.perf_counter()
     for ep in range(epochs):
-        lr_ep = 0.5 * lr * (1.0 + np.cos(np.pi * ep / epochs))
+        frac = ep / epochs if time_budget is None else min(1.0, (time.perf_counter() - t0) / time_budget)
+        lr_ep = 0.5 * lr * (1.0 + np.cos(np.pi * frac))
         order = rng.permutation(ntr)
         tot = 0.0
         for b0 in range(0, len(order), batch):
@@ -326,50 +362,47 @@ def train(data_dir, out_path, epochs=300, lr=1e-3, batch=8, seed=0, target="U", 
                 ts.append(torch.roll(Td[i], (sy, sx), dims=(1, 2)).contiguous())
             tot += net.train_step(xs, ts, lr=lr_ep) * len(idx)
         hist.append(tot / len(order))
-        if ep % 25 == 0 or ep == epochs - 1:
-            rec = dict(epoch=ep, loss=hist[-1], lr=lr_ep)
+        done = time_budget is not None and time.perf_counter() - t0 > time_budget
+        if ep % 25 == 0 or ep == epochs - 1 or done:
+            rec = dict(epoch=ep, loss=hist[-1], lr=lr_ep, seconds=round(time.perf_counter() - t0, 1))
             if n_val:
                 ve = val_errors()
                 rec.update(val_err_median=float(np.median(ve)), val_err_max=float(np.max(ve)))
             print(json.dumps(rec), flush=True)
+        if done:
+            break
     torch.cuda.synchronize()
-    np.savez(out_path, params=net.get_params(), Tbar=Tbar, scale=scale, feat_scale=feat_scale, target=target,
-             dilations=np.array(dilations), near_weight=near_weight, loss=np.array(hist),
-             train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0)
+    np.savez(out_path, params=net.get_params(), Tbar=Tbar.astype(np.float32), scale=scale, feat_scale=feat_scale,
+             target="E", dilations=np.array(dilations), near_weight=near_weight, loss=np.array(hist),
+             train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0, geometry=geometry,
+             epochs=len(hist))
     return hist
 
 
-def evaluate(weights, seeds, max_iter=400, ctx=None, with_mean=True):
+def evaluate(weights, seeds, max_iter=400, ctx=None, with_mean=True, geometry="study"):
     """Per held-out layout: SCF from the zero start, from the mean start (the
-    network's output replaced by zero: the symmetrized training mean, plus
-    the bare-donor potential for an electron-part model) and from the
-    learned start, with the learned start's inference time included."""
-    import torch
-    st = Study(ctx)
+    network's output replaced by zero: the symmetrized training mean plus
+    the bare-donor potential) and from the learned start, each start built
+    by the library with its time included; the fallback limit is ten times
+    the zero start's first residual."""
+    st = Study(ctx, geometry=geometry)
     start = st.surrogate(weights)
     out = []
     for sd in seeds:
-        p = W.study_slab(sd)
-        dmap = st.donor_map(p)
         zero = st.run(sd, None, max_iter)
         Ustar = zero["U"]
+        lim = 10.0 * zero["residuals"][0]
         rec = dict(seed=sd, zero=dict(iterations=zero["iterations"], seconds=zero["seconds"],
                                       converged=zero["converged"]),
                    zero_err0=float(Ustar.abs().max()))
         if with_mean:
-            Um = start.Tbar + (st.bare_potential(dmap) if start.target == "E" else 0.0)
-            mean = st.run(sd, Um, max_iter, zero["residuals"][0], fallback=True)
+            mean = st.run(sd, start, max_iter, lim, mean_only=True)
             rec["mean"] = dict(iterations=mean["iterations"], seconds=mean["seconds"], converged=mean["converged"],
-                               fell_back=mean["fell_back"], err0=float((Um - Ustar).abs().max()))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        U0 = start(dmap)
-        torch.cuda.synchronize()
-        t_inf = time.perf_counter() - t0
-        learned = st.run(sd, U0, max_iter, zero["residuals"][0], fallback=True)
-        rec["learned"] = dict(iterations=learned["iterations"], seconds=learned["seconds"] + t_inf,
-                              inference_seconds=t_inf, converged=learned["converged"],
-                              fell_back=learned["fell_back"], err0=float((U0 - Ustar).abs().max()),
+                               fell_back=mean["fell_back"], err0=float((mean["U0"] - Ustar).abs().max()))
+        learned = st.run(sd, start, max_iter, lim)
+        rec["learned"] = dict(iterations=learned["iterations"], seconds=learned["seconds"],
+                              start_seconds=learned["start_seconds"], converged=learned["converged"],
+                              fell_back=learned["fell_back"], err0=float((learned["U0"] - Ustar).abs().max()),
                               fixed_point_diff=float((learned["U"] - Ustar).abs().max()))
         out.append(rec)
         print(json.dumps(rec), flush=True)
@@ -394,6 +427,7 @@ def summarize(records):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--geometry", choices=sorted(GEOMETRIES), default="study")
     sub = ap.add_subparsers(dest="cmd", required=True)
     g = sub.add_parser("gen")
     g.add_argument("--out", required=True)
@@ -404,18 +438,17 @@ def main():
     k.add_argument("--out", required=True)
     k.add_argument("sources", nargs="+", help="layout directories or packed files")
     t = sub.add_parser("train")
-    t.add_argument("--data", required=True)
+    t.add_argument("--data", required=True, help="packed layouts (pack)")
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=300)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--batch", type=int, default=8)
     t.add_argument("--seed", type=int, default=0)
-    t.add_argument("--target", choices=("U", "E"), default="U",
-                   help="U: the converged potential; E: its electron part (minus the bare-donor potential)")
     t.add_argument("--val", type=int, default=0, help="hold out this many layouts and report their start error")
     t.add_argument("--dilations", default="1,2,4,1", help="one dilation per layer")
     t.add_argument("--near-weight", type=float, default=0.0,
                    help="extra loss weight on the atoms next to the donor plane")
+    t.add_argument("--budget", type=float, default=None, help="stop training after this many seconds")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="1000:1016")
@@ -423,14 +456,15 @@ def main():
     e.add_argument("--out", default=None)
     a = ap.parse_args()
     if a.cmd == "gen":
-        generate(a.out, _seeds(a.seeds), a.max_iter, a.budget)
+        generate(a.out, _seeds(a.seeds), a.max_iter, a.budget, geometry=a.geometry)
     elif a.cmd == "pack":
         print(json.dumps(dict(layouts=pack(a.out, a.sources))), flush=True)
     elif a.cmd == "train":
-        train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.target, a.val,
-              dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight)
+        train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.val,
+              dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight,
+              geometry=a.geometry, time_budget=a.budget)
     else:
-        recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean)
+        recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean, geometry=a.geometry)
         s = summarize(recs)
         print(json.dumps(dict(summary=s)), flush=True)
         if a.out:

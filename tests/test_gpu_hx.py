@@ -304,3 +304,34 @@ def test_tabulated_lanczos_c1(ctx):
     a1, b1, _ = tbh.lanczos_run(h, 30, p.v0, reorth=False)
     a2, b2, _ = tbh.lanczos_run(hs, 30, p.v0, reorth=False)
     assert np.abs(a1 - a2).max() < 1e-10 and np.abs(b1 - b2).max() < 1e-10
+
+
+def test_handles_destroyed_in_any_order():
+    """Contexts, hams, SCF loops and batches may be destroyed in any order
+    (a child keeps its parent alive until it is destroyed itself): here the
+    context goes first, then the ham, then the loop that uses the ham, and
+    the loop still steps between the two."""
+    import ctypes as C
+    import torch
+    lib = tbh.lib()
+    p = W.c5_slab(0, nx=2, ny=2, nz=4, n_donors=2)
+    ge = p.extra["gap"]
+    ctx = tbh.Context(0)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64"))
+    scf = tbh.SCF(h, p.extra["grid"], p.extra["donor_atoms"], p.v0, ge["mid"], ge["cbm"], W.H_GRID_NM,
+                  n_cand=32, lanczos_iter=p.dim)
+    X = torch.zeros((p.dim, 16), dtype=torch.float32, device="cuda")
+    hm = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f32", multi_vector=True))
+    b = tbh.Batch(ctx, [hm], [X], [torch.empty_like(X)])
+    # destroy through the ABI directly, parents first
+    assert lib.tbh_ctx_destroy(ctx.h) == tbh.TBH_OK
+    ctx.h = None
+    assert lib.tbh_ham_destroy(hm.h) == tbh.TBH_OK
+    hm.h = None
+    b.apply()
+    assert lib.tbh_ham_destroy(h.h) == tbh.TBH_OK
+    h.h = None
+    r = scf.step()
+    assert np.isfinite(r["residual"])
+    scf.close()
+    b.close()

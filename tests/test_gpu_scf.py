@@ -78,3 +78,72 @@ def test_scf_iterates_match_oracle(ctx, fixed):
         assert abs(r["residual"] - ro["residuals"][t]) < 1e-8
         assert abs(r["fermi"] - ro["Ef"][t]) < 1e-8
         assert abs(r["electrons"] - (len(donors) if not fixed else r["electrons"])) < 1e-8
+
+
+def _dense_step(p, grid, U, T_K=4.0):
+    """One step of the oracle's loop body at potential U (dense eigenpairs,
+    Fermi level by neutrality, CG Poisson): its output potential."""
+    from oracle import tb as T
+    blk = T.build_blocks(p)
+    H0 = T.csr_hamiltonian(blk).toarray()
+    nodes = S.node_index(p.pos_q, grid)
+    nx, ny, nz = grid
+    nd = np.zeros(nx * ny * nz)
+    np.add.at(nd, nodes[p.extra["donor_atoms"]], 1.0)
+    o = S.loop_body(H0, blk["n_o"], nodes, nd, U, grid, p.extra["gap"]["mid"], float(len(p.extra["donor_atoms"])),
+                    S.KB_EV * T_K, W.H_GRID_NM, 11.7, None, 1e-12)
+    return o["U_out"]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["lanczos_cgs2", "filtered_block"])
+def test_scf_production_setting_is_an_oracle_fixed_point(ctx, mode):
+    """The study slab (3x3x8 cells, 9 donors, 4 K) in the production setting:
+    FP32 H with its FP64 copy, linear mixing 0.05 to 1e-4 eV, and either 64
+    candidates of 800 CGS2 Lanczos steps or the filtered block solver (block
+    64).  The converged potential is a fixed point of one dense FP64 oracle
+    step: |U_out - U| < 1e-4 eV at every node."""
+    import torch
+    p = W.study_slab(1003)
+    ge = p.extra["gap"]
+    grid = p.extra["grid"]
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f32", keep_f64=True, multi_vector=(mode == 1)))
+    kw = dict(mix_alpha=0.05, tol_eV=1e-4, res_tol=1e-4, T_K=4.0)
+    if mode == 0:
+        kw.update(n_cand=64, lanczos_iter=800)
+    else:
+        kw.update(eig_mode=1, block=64, filter_degree=20, filter_degree_cold=80, filter_max_iter=60, k_states=40,
+                  e_vbm=ge["vbm"])
+    scf = tbh.SCF(h, grid, p.extra["donor_atoms"], p.v0, ge["mid"], ge["cbm"], W.H_GRID_NM, **kw)
+    r = scf.run(400)
+    print(f"mode {mode}: steps {r['iterations']} residual {r['residual']:.2e} seconds {r['seconds']:.2f}", flush=True)
+    assert r["converged"]
+    U = scf.potential().cpu().numpy()
+    U_out = _dense_step(p, grid, U)
+    d = np.abs(U_out - U).max()
+    print(f"dense oracle step from the GPU's U: max |U_out - U| = {d:.2e} eV", flush=True)
+    assert d < 1e-4
+
+
+def test_filtered_eigs_lowest_conduction_states(ctx):
+    """Filtered subspace iteration on (H - s)^2 (s three quarters into the
+    bulk gap) on a 3x3x20-cell slab: the 40 lowest conduction states equal
+    the reference spectrum's to 1e-6 eV (degenerate copies counted), with FP64
+    residuals of the returned unit vectors <= 1e-4 eV."""
+    from scipy.sparse.linalg import eigsh
+    from oracle import tb as T
+    p = W.c5_slab(1000, nx=3, ny=3, nz=20, n_donors=9)
+    ge = p.extra["gap"]
+    H = T.hamiltonian(p)
+    # reference: shift-invert Lanczos (ARPACK) on the FP64 CSR H below the band edge
+    ev = np.sort(eigsh(H, k=80, sigma=ge["cbm"] - 0.5, which="LM", return_eigenvectors=False))
+    want = ev[ev > ge["mid"]][:40]
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f32", keep_f64=True, multi_vector=True))
+    s = ge["vbm"] + 0.75 * (ge["cbm"] - ge["vbm"])
+    r = tbh.filtered_eigs(h, s, 40, 64, degree=40, degree_cold=80, max_iter=60, want_vectors=True)
+    print("report", r["report"], flush=True)
+    assert r["report"]["n_found"] == 40
+    assert np.abs(r["evals"] - want).max() < 1e-6
+    Y = r["vectors"].cpu().numpy()
+    R = (H @ Y.T) - Y.T * r["evals"][None, :]
+    assert np.linalg.norm(R, axis=0).max() < 1e-4
+    assert np.abs(Y @ Y.T - np.eye(40)).max() < 1e-5

@@ -1,14 +1,16 @@
-"""The trained start-potential surrogate against the plain method on
-donor layouts it was not trained on (seeds outside the training range), and
-the fallback rule, forced from the host.
+"""The trained start-potential surrogate against the plain method on donor
+layouts it was not trained on (seeds outside the training range), the start
+built by the library (tbh_scf_set_start) against the same arithmetic written
+out with torch, and the fallback rule.
 
 The network is the committed one, trained with the library's own kernels
 on converged plain-method potentials of the study slab (3x3x8 cells, 9
-donors, 4 K).  Bars: the learned start's max-norm error against the
-converged potential is at most a tenth of the zero start's, the loop from it
-converges in fewer steps, and both starts reach the same fixed point
-(within 1e-3 eV).  A start far from any solution (-60 eV everywhere) trips
-the "first residual > 10x the zero start's" rule and the loop still
+donors, 4 K).  Bars: the device start equals the torch assembly to 1e-5 eV;
+the learned start's max-norm error against the converged potential is at
+most a tenth of the zero start's, the loop from it converges in fewer steps,
+and both starts reach the same fixed point (within 1e-3 eV).  A start far
+from any solution (-60 eV below the bare-donor potential) trips the "first
+residual > 10x the zero start's" rule inside the library and the loop still
 converges from zero.
 """
 import os
@@ -46,17 +48,39 @@ def test_bare_potential_is_poisson_of_donors(study):
     assert torch.allclose(u2, 2 * u1, rtol=1e-8, atol=1e-10)
 
 
+@pytest.mark.parametrize("kind", ["learned", "mean"])
+def test_device_start_equals_torch_assembly(study, kind):
+    """U0 = U_bare + mean (+ scale * the average over the four point
+    operations of op^-1 net(op x)) built by tbh_scf_set_start equals the
+    same formula evaluated here with torch index operations and the
+    network's forward entry point."""
+    import torch
+    start = study.surrogate(WEIGHTS)
+    seed = 2003
+    p = W.study_slab(seed)
+    dmap = study.donor_map(p)
+    rec = study.run(seed, start, 1, mean_only=(kind == "mean"))
+    U0 = rec["U0"]
+    ub = study.bare_potential(dmap)
+    want = ub + start.Tbar.double()
+    if kind == "learned":
+        x = study.inputs(dmap, start.feat_scale)
+        y = sum(inv(start.net.forward(op(x).contiguous())) for op, inv in S.point_ops()) / 4.0
+        want = want + start.scale * y.double()
+    d = float((U0 - want).abs().max())
+    print(f"{kind}: max |U0_device - U0_torch| = {d:.2e} eV", flush=True)
+    assert d < 1e-5
+
+
 def test_learned_start_beats_zero_start(study):
     start = study.surrogate(WEIGHTS)
     for seed in (2000, 2001):
         assert seed not in start.train_seeds
-        p = W.study_slab(seed)
         zero = study.run(seed, None, 400)
         assert zero["converged"]
-        U0 = start(study.donor_map(p))
-        e_learned = float((U0 - zero["U"]).abs().max())
+        learned = study.run(seed, start, 400, 10 * zero["residuals"][0])
+        e_learned = float((learned["U0"] - zero["U"]).abs().max())
         e_zero = float(zero["U"].abs().max())
-        learned = study.run(seed, U0, 400, zero["residuals"][0], fallback=True)
         print(f"seed {seed}: err0 zero {e_zero:.3f} learned {e_learned:.4f} eV; steps zero "
               f"{zero['iterations']} learned {learned['iterations']}", flush=True)
         assert e_learned < 0.1 * e_zero
@@ -70,7 +94,7 @@ def test_fallback_on_far_start(study):
     seed = 2002
     nx, ny, nz = study.grid
     zero_first = study.run(seed, None, 1)["residuals"][0]
-    bad = torch.full((nz, ny, nx), -60.0, dtype=torch.float64, device="cuda")
-    r = study.run(seed, bad, 400, zero_first, fallback=True)
+    bad = torch.full((nz, ny, nx), -60.0, dtype=torch.float32, device="cuda")
+    r = study.run(seed, None, 400, 10 * zero_first, fixed_start=bad)
     assert r["fell_back"]
     assert r["converged"]
