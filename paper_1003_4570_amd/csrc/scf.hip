@@ -610,11 +610,12 @@ void Scf::set_start(const tbh_scf_start& sp) {
 
 void Scf::set_potential(const double* Ud) {
     hipStream_t st = h->ctx->stream;
-    if (Ud && Ud != U.as<double>())
-        TBH_HIP(hipMemcpyAsync(U.p, Ud, n_nodes * 8, hipMemcpyDeviceToDevice, st));
-    else
+    // null: the zero start; the loop's own buffer (a start built in place): kept as it is
+    if (!Ud)
         hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), 0.0,
                            U.as<double>());
+    else if (Ud != U.as<double>())
+        TBH_HIP(hipMemcpyAsync(U.p, Ud, n_nodes * 8, hipMemcpyDeviceToDevice, st));
     // phi guess for the next Poisson solve: -U
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), -1.0,
                        phi.as<double>());

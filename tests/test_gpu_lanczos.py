@@ -121,27 +121,26 @@ def test_c1_eigs_without_reorth(ctx):
 
 def test_fp32_interior_without_reorth_hardwall_so(ctx):
     """C2 recipe (its gap-accepted parameter set) at 3^3 cells, sigma at
-    mid-gap: the FP32 recurrence without reorthogonalisation reaches
-    interior values (band-edge states); every reported value is within
-    1e-6 eV of the dense FP64 spectrum after refinement.  Coverage of the 4
-    nearest is printed, not graded (FP32 loses orthogonality sooner, so the
-    converged set near sigma can differ from FP64's)."""
+    mid-gap: the FP32 recurrence without reorthogonalisation reaches the
+    interior values (band-edge states).  With 3000 steps it covers the 4
+    distinct eigenvalues nearest sigma of the dense FP64 spectrum, each within
+    1e-6 eV after refinement (ghost copies, whose raw FP32 Ritz values differ
+    by more than the merge tolerance, merge by their Rayleigh quotients)."""
     ge = W._gap_entry(W.MODEL_SP3D5S, 1)
     p = W.problem_periodic_cube(3, seed=2, model=W.MODEL_SP3D5S, spin=1, periodic=(0, 0, 0),
                                 passivation=30.0, strain=True, prec="f32", sigma=ge["mid"], k=4,
                                 param_seed=ge["seed"])
     ev = np.linalg.eigvalsh(T.hamiltonian(p).toarray())
     h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, keep_f64=True))
-    r = tbh.lanczos_eigs(h, p.sigma, 4, 1500, p.v0, reorth=False, n_cand=128)
+    r = tbh.lanczos_eigs(h, p.sigma, 4, 3000, p.v0, reorth=False, n_cand=256)
     n = r["report"]["n_found"]
     u = _distinct(ev, 1e-6)
     want = np.sort(u[np.argsort(np.abs(u - p.sigma), kind="stable")[:4]])
-    cover = sum(np.abs(r["refined"] - w).min() < 1e-6 for w in want)
+    cover = sum(np.abs(r["refined"] - w).min() < 1e-6 for w in want) if n else 0
     print("found", n, "refined", r["refined"], "want", want, "copies", r["copies"], "coverage", cover,
           flush=True)
-    assert n >= 2
-    for e in r["refined"]:
-        assert np.abs(ev - e).min() < 1e-6
+    assert n == 4 and cover == 4
+    assert np.abs(np.sort(r["refined"]) - want).max() < 1e-6
 
 
 def test_full_krylov_tiny_cell(ctx):

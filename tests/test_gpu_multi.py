@@ -117,3 +117,39 @@ def test_batched_graph_equals_separate_and_oracle(ctx, tmp_path):
         torch.cuda.synchronize()
         for a, y in zip(got, Ys):
             assert np.array_equal(a, y.cpu().numpy())
+
+
+def test_c4_full_batch_sampled_rows(ctx):
+    """The full batched workload (48 periodic cells with edges 2..12, 4
+    k-points each, sp3s* with spin-orbit, 16 complex right-hand vectors) in
+    one graph launch: sampled atoms of every cell and k-point, all 16
+    columns, against the oracle's rows computed atom by atom (relative 1e-5
+    per sampled row block, and the per-row rounding bound)."""
+    import torch
+    items = W.c4_batch(0)
+    hams, Xs, Ys = [], [], []
+    for prob, x in items:
+        hams.append(tbh.build_hamiltonian(ctx, **tbh.problem_args(prob, multi_vector=True)))
+        Xs.append(torch.from_numpy(x.astype(np.complex64)).cuda())
+        Ys.append(torch.empty_like(Xs[-1]))
+    b = tbh.Batch(ctx, hams, Xs, Ys)
+    b.apply()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for (prob, x), X, Y in zip(items, Xs, Ys):
+        atoms = np.unique(np.concatenate([[0, prob.n_atoms - 1], rng.integers(0, prob.n_atoms, 3)]))
+        Xh = X.cpu().numpy().astype(np.complex128)
+        Yh = Y.cpu().numpy().reshape(prob.n_atoms, 10, 16)
+        nbr, wrap = T.find_neighbours(prob.pos_q, prob.box_q, prob.periodic)
+        for c in range(16):
+            ref = T.hx_rows(prob, atoms, Xh[:, c], nbr=nbr, wrap=wrap)
+            got = Yh[atoms, :, c]
+            e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            worst = max(worst, e)
+            # per row: complex products (4 real terms) over 50 entries, one rounding of each stored element
+            bound = 2 * 51 * 2.0 ** -24 * T.hx_rows(prob, atoms, np.abs(Xh[:, c]), nbr=nbr, wrap=wrap,
+                                                       absolute=True).real
+            assert (np.abs(got - ref) <= bound + 1e-30).all()
+    print("c4 full batch: worst sampled relative error", worst, flush=True)
+    assert worst <= 1e-5

@@ -144,3 +144,15 @@ def test_deflation_vector_generator():
     s = BL.splitmix64(np.arange(100_000, dtype=np.uint64))
     assert np.unique(s).size == s.size
     assert not np.array_equal(BL.deflation_vector(1, 0, 16, 64, False), BL.deflation_vector(1, 1, 16, 64, False))
+
+
+def test_splitmix64_published_outputs():
+    """The counter form mix(x + golden gamma) reproduces the first three
+    outputs of the stateful SplitMix64 generator seeded with 0 (Steele, Lea
+    and Flood, OOPSLA 2014; the values quoted with the reference C code of the
+    xoshiro family): output k is mix(k * gamma)."""
+    g = np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        x = np.array([0, g, g * np.uint64(2)], dtype=np.uint64)
+        s = BL.splitmix64(x)
+    assert [int(v) for v in s] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
