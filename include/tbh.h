@@ -425,6 +425,18 @@ int tbh_poisson_solve(tbh_ctx* ctx, const int32_t grid[3], double h_nm, double e
                       double* phi_dev, double rel_tol, int32_t max_iter, int32_t* iters,
                       double* rel_res);
 
+/* The same solve without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, result and status as tbh_poisson_solve;
+ * additionally TBH_EINVAL when nx*ny*nz exceeds 262,144 (2^18) nodes.  Its
+ * scratch (b, the CG vectors r, p, Ap and reduction partials: 8.5 MB) is one
+ * static device array per GPU, held until the process ends and shared by
+ * every call on that GPU: calls that overlap on one GPU (several streams or
+ * threads) race on it. */
+int tbh_poisson_solve_noalloc(tbh_ctx* ctx, const int32_t grid[3], double h_nm, double eps_r,
+                              const double* rho_dev, double* phi_dev, double rel_tol, int32_t max_iter,
+                              int32_t* iters, double* rel_res);
+
 /* ------------------------------------------------------------------------
  * Self-consistent Schrodinger-Poisson loop (Sec. III-A; the application of
  * Sec. III-B is a P delta layer in Si at 4 K).

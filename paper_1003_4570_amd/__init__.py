@@ -155,6 +155,9 @@ _SIGS = [
     ("tbh_poisson_solve", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_double, C.c_double,
                                     C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    ("tbh_poisson_solve_noalloc", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_double, C.c_double,
+                                            C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     ("tbh_scf_create", C.c_int, [C.c_void_p, C.POINTER(tbh_scf_opts), C.POINTER(C.c_void_p)]),
     ("tbh_scf_destroy", C.c_int, [C.c_void_p]),
     ("tbh_scf_set_potential", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -610,10 +613,13 @@ def tridiag_eig(ctx: Context, diag, off):
     return th
 
 
-def poisson_solve(ctx: Context, grid, h_nm, eps_r, rho, phi=None, rel_tol=1e-10, max_iter=100000):
+def poisson_solve(ctx: Context, grid, h_nm, eps_r, rho, phi=None, rel_tol=1e-10, max_iter=100000,
+                  noalloc=False):
     """FP64 CG for -eps0 eps_r Lap_h phi = rho on the device.  rho: [nz, ny, nx]
     float64 device tensor (e/nm^3); phi: initial guess (updated in place) or
-    None (zero).  Returns (phi, iterations, relative residual)."""
+    None (zero).  noalloc selects the entry point that allocates no device
+    memory (grids up to 2^18 nodes).  Returns (phi, iterations, relative
+    residual)."""
     import torch
     if phi is None:
         phi = torch.zeros_like(rho)
@@ -624,7 +630,8 @@ def poisson_solve(ctx: Context, grid, h_nm, eps_r, rho, phi=None, rel_tol=1e-10,
     g = (C.c_int32 * 3)(*[int(v) for v in grid])
     it = C.c_int32(0)
     rr = C.c_double(0.0)
-    rc = lib().tbh_poisson_solve(ctx.h, g, float(h_nm), float(eps_r), C.c_void_p(rho.data_ptr()),
+    fn = lib().tbh_poisson_solve_noalloc if noalloc else lib().tbh_poisson_solve
+    rc = fn(ctx.h, g, float(h_nm), float(eps_r), C.c_void_p(rho.data_ptr()),
             C.c_void_p(phi.data_ptr()), float(rel_tol), int(max_iter),
             C.byref(it), C.byref(rr))
     if rc not in (TBH_OK, TBH_ENOCONV):

@@ -121,6 +121,7 @@ int tbh_ctx_create(int device, void* stream, tbh_ctx** out) {
         TBH_HIP(hipGetDeviceCount(&n));
         TBH_REQUIRE(device >= 0 && device < n, "device index out of range");
         TBH_HIP(hipSetDevice(device));
+        tbh::noalloc_setup(device);   // scratch address of the allocation-free entry point
         auto c = std::make_unique<tbh_ctx>();
         c->device = device;
         c->stream = static_cast<hipStream_t>(stream);

@@ -233,7 +233,10 @@ void hx_launch(const Layout& lay, bool f64, const HxArgs& a, hipStream_t s);
 
 // error slot shared by every C ABI translation unit (thread-local)
 void set_error(const std::string& msg);
-
+// allocation-free entry points: look up this device's scratch address once
+// (the device must be current); the address, or null before set-up
+void noalloc_setup(int device);
+double* noalloc_scratch(int device);
 
 // Run f, translating exceptions into a status code and the error message.
 template <typename F>
