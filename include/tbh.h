@@ -494,6 +494,27 @@ typedef struct {
     int32_t filter_max_iter;
     int32_t k_states;         /* <= block */
     double e_vbm;             /* bulk valence-band maximum (eV) */
+    /* update of step 5: 0 = linear mixing; 1 = Newton-Raphson on
+     * G(U) = A U - kappa (n(U) - N_D) = 0 (A = -Lap_h, kappa = 1 / (h^3 eps0
+     * eps_r); Sec. III-A obtains the potential by Newton-Raphson).  The
+     * Jacobian J = A - kappa chi takes the density response chi = dn/dU of
+     * first-order perturbation theory over the newton_states lowest filled-
+     * class (CB-like) states of the step,
+     *   chi v = 2 sum_ik g_ik rho_ik (rho_ik . v) - 2 d (d . v) / sum_i f'_i,
+     *   rho_ik(atom) = sum_alpha psi_i psi_k, g_ik = (f_i - f_k)/(E_i - E_k),
+     *   g_ii = f'_i, d = sum_i f'_i rho_ii (the last term only under
+     *   neutrality),
+     * with occupations smeared at newton_kT (eV) inside chi only; J d = -G is
+     * solved by Jacobi-preconditioned CG (FP64) to newton_cg_tol, and the
+     * steps are combined by Anderson mixing over the last anderson_depth
+     * steps.  The residual and the stopping rule stay those of step 5.
+     * Real H only. */
+    int32_t update_mode;
+    int32_t newton_states;    /* 1..128 */
+    double newton_kT;         /* > 0 */
+    int32_t anderson_depth;   /* 0..8 */
+    double newton_cg_tol;
+    int32_t newton_cg_max_iter;
 } tbh_scf_opts;
 
 typedef struct {
@@ -511,6 +532,9 @@ typedef struct {
     double sigma;             /* Lanczos target of the step (eV) */
     double seconds, eig_seconds, poisson_seconds;
     int32_t fell_back;        /* 1 if this step abandoned a start potential for the zero start */
+    int32_t newton_cg_iters;  /* update_mode 1: CG iterations of the Newton solve (0 otherwise) */
+    int32_t newton_pairs;     /* update_mode 1: state pairs in chi after pruning */
+    double newton_seconds;    /* update_mode 1: time of the update */
 } tbh_scf_report;
 
 /* The SCF object keeps h (which must outlive it, and must have an FP64 copy)

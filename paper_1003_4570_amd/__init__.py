@@ -101,7 +101,9 @@ class tbh_scf_opts(C.Structure):
                 ("donor_atoms", C.POINTER(C.c_int32)), ("n_donors", C.c_int32),
                 ("v0", C.POINTER(C.c_double)), ("eig_mode", C.c_int32), ("block", C.c_int32),
                 ("filter_degree", C.c_int32), ("filter_degree_cold", C.c_int32), ("filter_max_iter", C.c_int32),
-                ("k_states", C.c_int32), ("e_vbm", C.c_double)]
+                ("k_states", C.c_int32), ("e_vbm", C.c_double), ("update_mode", C.c_int32),
+                ("newton_states", C.c_int32), ("newton_kT", C.c_double), ("anderson_depth", C.c_int32),
+                ("newton_cg_tol", C.c_double), ("newton_cg_max_iter", C.c_int32)]
 
 
 class tbh_scf_report(C.Structure):
@@ -110,7 +112,8 @@ class tbh_scf_report(C.Structure):
                 ("electrons", C.c_double), ("cg_iters", C.c_int32), ("cg_rel_res", C.c_double),
                 ("lanczos_steps", C.c_int32), ("u_min", C.c_double), ("sigma", C.c_double),
                 ("seconds", C.c_double),
-                ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double), ("fell_back", C.c_int32)]
+                ("eig_seconds", C.c_double), ("poisson_seconds", C.c_double), ("fell_back", C.c_int32),
+                ("newton_cg_iters", C.c_int32), ("newton_pairs", C.c_int32), ("newton_seconds", C.c_double)]
 
 
 class tbh_scf_start(C.Structure):
@@ -647,7 +650,9 @@ class SCF(_Handle):
     def __init__(self, ham: Hamiltonian, grid, donor_atoms, v0, sigma_mid, e_cbm, h_nm, eps_r=11.7,
                  T_K=4.0, mix_alpha=0.1, tol_eV=1e-4, n_cand=48, lanczos_iter=600, res_tol=1e-4,
                  cg_tol=1e-12, cg_max_iter=20000, fermi_fixed=None, eig_mode=0, block=64, filter_degree=20,
-                 filter_degree_cold=60, filter_max_iter=20, k_states=40, e_vbm=float("nan")):
+                 filter_degree_cold=60, filter_max_iter=20, k_states=40, e_vbm=float("nan"), update_mode=0,
+                 newton_states=64, newton_kT=0.01, anderson_depth=4, newton_cg_tol=1e-6,
+                 newton_cg_max_iter=20000):
         self._adopt(ham)
         self.ham = ham
         self.grid = tuple(int(g) for g in grid)
@@ -660,7 +665,8 @@ class SCF(_Handle):
                          int(cg_max_iter), _p(self._donors, C.c_int32), int(self._donors.size),
                          self._v0.ctypes.data_as(C.POINTER(C.c_double)), int(eig_mode), int(block),
                          int(filter_degree), int(filter_degree_cold), int(filter_max_iter), int(k_states),
-                         float(e_vbm))
+                         float(e_vbm), int(update_mode), int(newton_states), float(newton_kT),
+                         int(anderson_depth), float(newton_cg_tol), int(newton_cg_max_iter))
         h = C.c_void_p()
         _check(lib().tbh_scf_create(ham.h, C.byref(o), C.byref(h)))
         self.h = h

@@ -116,17 +116,19 @@ int tbh_scf_run(tbh_scf* s, int32_t max_iter, tbh_scf_report* rep) {
         TBH_REQUIRE(s && max_iter >= 1, "null scf or max_iter < 1");
         TBH_HIP(hipSetDevice(s->h->ctx->device));
         tbh_scf_report r{};
-        double secs = 0.0, es = 0.0, ps = 0.0;
+        double secs = 0.0, es = 0.0, ps = 0.0, ns = 0.0;
         for (int it = 0; it < max_iter; ++it) {
             s->step(r);
             secs += r.seconds;
             es += r.eig_seconds;
             ps += r.poisson_seconds;
+            ns += r.newton_seconds;
             if (r.converged || !std::isfinite(r.residual)) break;
         }
         r.seconds = secs;
         r.eig_seconds = es;
         r.poisson_seconds = ps;
+        r.newton_seconds = ns;
         if (rep) *rep = r;
         if (!r.converged) status = TBH_ENOCONV;
     });

@@ -17,7 +17,8 @@
 // operand from the FP16 weights.  Backward-data is the forward convolution
 // of the upstream gradient with tap-reversed, channel-transposed weights,
 // with the previous layer's ReLU mask applied in the epilogue.  The weight
-// gradient is an FP32 reduction over voxels in fixed order.  The loss
+// gradient is a third implicit GEMM on the matrix cores (K = voxels, staged
+// through LDS), reduced over workgroups in fixed order.  The loss
 // gradient is scaled by the voxel count (sum of squares) so FP16 gradients
 // stay in range; the optimizer divides it back out.
 #include <cmath>
@@ -130,28 +131,116 @@ __global__ __launch_bounds__(TPB) void k_conv(Geo g, int dil, const _Float16* __
     }
 }
 
-// partial weight gradients: part[chunk][w], w = (co, tap, ci) (+ COUT bias
-// entries at the end), over the chunk's voxels
-template <int CIN, int COUT>
-__global__ void k_conv_wgrad(Geo g, int dil, const _Float16* __restrict__ in, const _Float16* __restrict__ dout,
-                             int64_t chunk, float* part) {
-    constexpr int NW = COUT * 27 * CIN;
-    const int w = blockIdx.x * TPB + threadIdx.x;
-    if (w >= NW + COUT) return;
-    const int64_t c0 = int64_t(blockIdx.y) * chunk;
-    const int64_t c1 = c0 + chunk < g.nvox ? c0 + chunk : g.nvox;
-    float acc = 0.f;
-    if (w < NW) {
-        const int co = w / (27 * CIN), rem = w % (27 * CIN), tap = rem / CIN, ci = rem % CIN;
-        for (int64_t v = c0; v < c1; ++v) {
-            const int64_t s = shifted_voxel(g, v, tap, dil);
-            if (s >= 0) acc += float(dout[v * COUT + co]) * float(in[s * CIN + ci]);
+// Weight gradient on the matrix cores: dW[co][n] = sum_v dout[v][co] in[shift_tap(v)][ci]
+// with n = tap * CIN + ci (the [c_out][tap][c_in] layout), and the bias
+// gradient as one more column n = 27 CIN whose input is 1 on every voxel.
+// As a GEMM: M = output channels, N = 27 CIN + 1, K = voxels.  Each
+// workgroup walks chunks of 64 voxels (grid-stride over blockIdx.x); per
+// chunk the upstream gradient is staged once into LDS as [co][64 voxels]
+// (the A operand, 4 consecutive voxels per 8-byte read), and each wave
+// stages, per column tile of 16, the shifted input values as [16][64 voxels]
+// (the B operand).  blockIdx.y selects a group of 4 TPW column tiles (TPW per
+// wave).  Partial sums stay in the accumulators over the workgroup's chunks
+// and are written to part[blockIdx.x][w] (w = co * 27 CIN + n, then the
+// biases), which k_reduce_chunks sums over blockIdx.x in fixed order.
+template <int CIN, int COUT, int TPW>
+__global__ __launch_bounds__(TPB) void k_conv_wgrad(Geo g, int dil, const _Float16* __restrict__ in,
+                                                    const _Float16* __restrict__ dout, float* __restrict__ part) {
+    constexpr int N = 27 * CIN;             // weight columns; column N is the bias
+    constexpr int NW = COUT * N;
+    constexpr int COT = (COUT + 15) / 16;   // row tiles
+    constexpr int NTN = (N + 1 + 15) / 16;  // column tiles
+    __shared__ _Float16 sD[COT * 16][64];
+    __shared__ _Float16 sB[TPB / 64][16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = lane >> 4, c16 = lane & 15;
+    const int tile0 = (blockIdx.y * (TPB / 64) + wave) * TPW;
+    f4 acc[TPW][COT];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int c = 0; c < COT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t nchunks = (g.nvox + 63) / 64;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t v0 = ch * 64;
+        __syncthreads();   // the previous chunk's LDS reads are done
+        for (int idx = threadIdx.x; idx < COT * 16 * 64; idx += TPB) {
+            const int co = idx >> 6, vv = idx & 63;
+            const int64_t v = v0 + vv;
+            sD[co][vv] = (co < COUT && v < g.nvox) ? dout[v * COUT + co] : _Float16(0);
         }
-    } else {
-        const int co = w - NW;
-        for (int64_t v = c0; v < c1; ++v) acc += float(dout[v * COUT + co]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int n0 = (tile0 + t) * 16;
+            // this lane stages voxel v0 + lane for the tile's 16 columns
+            const int64_t v = v0 + lane;
+            const bool vin = v < g.nvox;
+            if constexpr (CIN % 16 == 0) {
+                // the tile's 16 columns are 16 consecutive channels of one tap
+                const int tap = n0 / CIN, ci0 = n0 % CIN;
+                _Float16 vals[16];
+                if (n0 < N) {
+                    const int64_t sv = vin ? shifted_voxel(g, v, tap, dil) : -1;
+                    if (sv >= 0) {
+                        const h4* src = reinterpret_cast<const h4*>(in + sv * CIN + ci0);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const h4 x = src[e];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) vals[4 * e + u] = x[u];
+                        }
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < 16; ++jj) vals[jj] = _Float16(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < 16; ++jj) vals[jj] = (n0 + jj == N && vin) ? _Float16(1) : _Float16(0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) sB[wave][jj][lane] = vals[jj];
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int n = n0 + jj;
+                    _Float16 val = 0;
+                    if (vin && n < N) {
+                        const int64_t sv = shifted_voxel(g, v, n / CIN, dil);
+                        if (sv >= 0) val = in[sv * CIN + n % CIN];
+                    } else if (vin && n == N) {
+                        val = 1;
+                    }
+                    sB[wave][jj][lane] = val;
+                }
+            }
+            __syncthreads();   // sD and this tile's sB are staged
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const h4 b = *reinterpret_cast<const h4*>(&sB[wave][c16][ks * 16 + 4 * q]);
+#pragma unroll
+                for (int c = 0; c < COT; ++c) {
+                    const h4 a = *reinterpret_cast<const h4*>(&sD[c * 16 + c16][ks * 16 + 4 * q]);
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc[t][c], 0, 0, 0);
+                }
+            }
+            __syncthreads();   // sB is free for the next tile
+        }
     }
-    part[int64_t(blockIdx.y) * (NW + COUT) + w] = acc;
+    // D[i = 4 q + r][j = c16]: output channel c * 16 + 4 q + r, column tile * 16 + c16
+    float* out = part + int64_t(blockIdx.x) * (NW + COUT);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int n = (tile0 + t) * 16 + c16;
+        if (tile0 + t >= NTN || n > N) continue;
+#pragma unroll
+        for (int c = 0; c < COT; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = c * 16 + 4 * q + r;
+                if (co >= COUT) continue;
+                out[n < N ? co * N + n : NW + co] = acc[t][c][r];
+            }
+    }
 }
 
 // grad[w] += sum over chunks (fixed order)
@@ -240,14 +329,16 @@ void conv_launch(const Geo& g, int dil, const _Float16* in, const _Float16* W, c
     hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), dim3(blocks), dim3(TPB), 0, s, g, dil, in, W, b, mask, out);
 }
 
+// nblk workgroups along the voxels, each writing one partial gradient
 template <int CIN, int COUT>
-void wgrad_launch(const Geo& g, int dil, const _Float16* in, const _Float16* dout, float* part, int nchunk,
+void wgrad_launch(const Geo& g, int dil, const _Float16* in, const _Float16* dout, float* part, int nblk,
                   float* grad, hipStream_t s) {
     constexpr int NW = COUT * 27 * CIN + COUT;
-    const int64_t chunk = (g.nvox + nchunk - 1) / nchunk;
-    dim3 grid((NW + TPB - 1) / TPB, nchunk);
-    hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), grid, dim3(TPB), 0, s, g, dil, in, dout, chunk, part);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((NW + TPB - 1) / TPB), dim3(TPB), 0, s, part, nchunk, NW, grad);
+    constexpr int TPW = CIN >= 32 ? 4 : 1;
+    constexpr int NTN = (27 * CIN + 1 + 15) / 16;
+    constexpr int groups = (NTN + 4 * TPW - 1) / (4 * TPW);
+    hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT, TPW>), dim3(nblk, groups), dim3(TPB), 0, s, g, dil, in, dout, part);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((NW + TPB - 1) / TPB), dim3(TPB), 0, s, part, nblk, NW, grad);
 }
 
 }  // namespace
@@ -290,7 +381,9 @@ Net::Net(Ctx* c, int channels, int in_channels, int n_layers, const int* dilatio
     pred.alloc(size_t(nvox) * 4);
     dact[0].alloc(size_t(nvox) * C * 2);
     dact[1].alloc(size_t(nvox) * C * 2);
-    nchunk = int(std::min<int64_t>(64, std::max<int64_t>(1, nvox / 64)));
+    // workgroups of the weight gradient along the voxels (each 64-voxel chunk
+    // belongs to one of them); one partial gradient each
+    nchunk = int(std::min<int64_t>(256, std::max<int64_t>(1, (nvox + 63) / 64)));
     part.alloc(size_t(nchunk) * (int64_t(C) * 27 * C + C) * 4);
     dpart.alloc(4096 * 8);
     scalar.alloc(8 * 8);

@@ -29,6 +29,39 @@ void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, con
 void poisson_cg_bufs(hipStream_t st, const PoissonBufs& W, const int grid[3], double h, const double* b,
                      double* x, double rel_tol, int max_iter, int* iters, double* rel_res);
 
+// Newton-Raphson update of the loop's potential (newton.hip)
+struct NewtonWork {
+    DevBuf R, coef, pairs, sel, inv, fp, diag, d, va, tpart, a, minv, x, r, z, p, Ap, G, Xp, Fp, part, s, small, dX, dF;
+    bool have_prev = false;     // an iterate and step are stored for Anderson mixing
+    int count = 0, head = 0;    // stored differences, next slot
+    std::vector<double> gram;   // dF_l . dF_q of the stored differences
+    void reset();
+};
+struct NewtonIn {
+    const double* Y;            // states [.][ns] FP64 (stream order, real)
+    int64_t ns;
+    int n_o;
+    int64_t n_atoms;
+    const int64_t* node;        // atom -> grid node (stream order)
+    int grid[3];
+    double h, kappa;
+    const double* b;            // kappa (N_D - n) on the grid
+    std::vector<int> sel;       // states of chi (rows of Y), ascending energy
+    std::vector<double> E, inv_norm;   // their energies and 1 / |y|
+    double Ef, kT;              // Fermi level and the smearing of chi
+    bool fixed;                 // Fermi level given (no neutrality term)
+    double cg_tol;
+    int cg_max_iter;
+    int depth;                  // Anderson depth (0 = plain Newton steps)
+};
+struct NewtonOut {
+    int cg_iters = 0;
+    double cg_rel = 0.0;
+    int npairs = 0;
+};
+// one Newton-Raphson step from U (device grid, updated in place)
+void newton_update(hipStream_t st, NewtonWork& W, const NewtonIn& in, double* U, NewtonOut* out);
+
 struct Scf {
     Ham* h;
     tbh_scf_opts opt;
@@ -54,7 +87,10 @@ struct Scf {
     std::shared_ptr<BlWork> blw;
     std::shared_ptr<FsWork> fs;
     bool fs_warm = false, have_bounds = false;
+    DevBuf U_bounds;            // the potential the spectral bounds were taken at
     double emin_b = 0.0, emax_b = 0.0, last_res = 0.0;
+    // Newton-Raphson update (update_mode 1)
+    NewtonWork nw;
     Scf(Ham* h, const tbh_scf_opts& o);
     void set_potential(const double* U_dev);
     void step(tbh_scf_report& rep);

@@ -14,6 +14,7 @@
 // kernel with the fused p.Ap partial sums, one update kernel with the fused
 // r.r partial sums, and single-block scalar kernels; no host round trip per
 // iteration.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -331,6 +332,17 @@ __global__ void k_minmax(int64_t n, const double* U, double* part) {
     }
 }
 
+// partial max |U - U_ref| (reduced by k_mix_reduce into out[0])
+__global__ void k_drift(int64_t n, const double* U, const double* Uref, double* part) {
+    double mx = 0.0;
+    GRID_LOOP(i, n) mx = fmax(mx, fabs(U[i] - Uref[i]));
+    const double a = block_max1(mx);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
 __global__ void k_gather_atoms(int64_t n_atoms, const int64_t* node, const double* U, double* Ua) {
     GRID_LOOP(i, n_atoms) Ua[i] = U[node[i]];
 }
@@ -471,6 +483,13 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
                         h->has_mv && !h->cplx_h,
                     "filtered eigen-solve: block 16/32/64, 1 <= k_states <= block, degrees and filter_max_iter >= 1, "
                     "and a real H built with multi_vector = 1");
+    TBH_REQUIRE(o.update_mode == 0 || o.update_mode == 1, "update_mode must be 0 (linear mixing) or 1 (Newton)");
+    if (o.update_mode == 1)
+        TBH_REQUIRE(!h->cplx_h && o.newton_states >= 1 && o.newton_states <= 128 && o.newton_kT > 0 &&
+                        o.anderson_depth >= 0 && o.anderson_depth <= 8 && o.newton_cg_tol > 0 &&
+                        o.newton_cg_max_iter >= 1,
+                    "Newton update: real H, 1 <= newton_states <= 128, newton_kT > 0, 0 <= anderson_depth <= 8, "
+                    "newton_cg_tol > 0, newton_cg_max_iter >= 1");
     TBH_REQUIRE(o.n_donors >= 0 && (o.n_donors == 0 || o.donor_atoms), "bad donor list");
     TBH_REQUIRE(o.v0, "null start vector");
     n_nodes = int64_t(grid[0]) * grid[1] * grid[2];
@@ -620,8 +639,11 @@ void Scf::set_potential(const double* Ud) {
     hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), -1.0,
                        phi.as<double>());
     TBH_HIP(hipGetLastError());
-    // a new start: the previous step's filled states no longer locate the band edge
+    // a new start: the previous step's filled states no longer locate the band
+    // edge, and the Newton steps' history belongs to the old iterates
     have_prev = false;
+    nw.reset();
+    have_bounds = false;
     last_res = 0.0;
     start_kind = 0;
     since_start = 0;
@@ -669,7 +691,20 @@ void Scf::step(tbh_scf_report& rep) {
             blw = std::make_shared<BlWork>();
         }
         fs->ensure(h->dim, opt.block);
+        // the bounds hold while no potential value has moved by more than their
+        // 2 eV margin since they were taken (a diagonal change shifts every
+        // eigenvalue by at most its largest magnitude)
+        if (have_bounds) {
+            hipLaunchKernelGGL(k_drift, dim3(gn), dim3(TPB), 0, st, n_nodes, U.as<double>(), U_bounds.as<double>(), pt);
+            hipLaunchKernelGGL(k_mix_reduce, dim3(1), dim3(TPB), 0, st, pt, gn, out.as<double>() + 4);
+            double dr[2];
+            TBH_HIP(hipMemcpyAsync(dr, out.as<double>() + 4, 16, hipMemcpyDeviceToHost, st));
+            TBH_HIP(hipStreamSynchronize(st));
+            if (!(dr[0] <= 1.5)) have_bounds = false;
+        }
         if (!have_bounds) {
+            U_bounds.alloc(size_t(n_nodes) * 8);
+            TBH_HIP(hipMemcpyAsync(U_bounds.p, U.p, size_t(n_nodes) * 8, hipMemcpyDeviceToDevice, st));
             spectral_bounds(*h, &emin_b, &emax_b);
             // room for the potential to change over the loop
             emin_b -= 2.0;
@@ -687,7 +722,10 @@ void Scf::step(tbh_scf_report& rep) {
         so.min_iter = 1;
         so.max_iter = opt.filter_max_iter;
         so.k = opt.k_states;
-        so.res_tol = fs_warm ? std::max(opt.res_tol, 0.1 * last_res) : opt.res_tol;
+        // linear mixing moves U by a small fraction of the residual per step, so
+        // early states need not be sharper than a tenth of it; a Newton step can
+        // move U by the whole residual, so its states are held to a hundredth
+        so.res_tol = fs_warm ? std::max(opt.res_tol, (opt.update_mode == 0 ? 0.1 : 0.01) * last_res) : opt.res_tol;
         sigma = so.s;
         steps = filtered_solve(*h, *blw, *fs, so, fs_warm, nullptr, nullptr);
         fs_warm = true;
@@ -719,13 +757,66 @@ void Scf::step(tbh_scf_report& rep) {
     poisson_cg(st, pw, grid, opt.h_nm, b.as<double>(), phi.as<double>(), opt.cg_tol, opt.cg_max_iter, &cg_it,
                &cg_rel);
     const auto t2 = std::chrono::steady_clock::now();
+    // linear mixing (update_mode 0); the Newton update leaves U to newton_update
     hipLaunchKernelGGL(k_mix, dim3(gn), dim3(TPB), 0, st, n_nodes, phi.as<double>(), U.as<double>(),
-                       opt.mix_alpha, pt);
+                       opt.update_mode == 0 ? opt.mix_alpha : 0.0, pt);
     hipLaunchKernelGGL(k_mix_reduce, dim3(1), dim3(TPB), 0, st, pt, gn, out.as<double>() + 4);
     double o[8];
     TBH_HIP(hipMemcpyAsync(o, out.p, sizeof(o), hipMemcpyDeviceToHost, st));
     TBH_HIP(hipStreamSynchronize(st));
     TBH_HIP(hipGetLastError());
+    // a step whose filling could not place every electron (too few states in
+    // the eigen-solve's window) is not a solution, whatever its residual
+    const bool neutral_ok =
+        use_fixed || std::fabs(o[3] - double(opt.n_donors)) <= 1e-6 * std::max(1.0, double(opt.n_donors));
+    rep.newton_cg_iters = 0;
+    rep.newton_pairs = 0;
+    rep.newton_seconds = 0.0;
+    if (opt.update_mode == 1 && !(o[4] < opt.tol_eV && neutral_ok)) {
+        const auto tn = std::chrono::steady_clock::now();
+        // the filled-class states of the step (the same test as k_fermi), lowest first
+        std::vector<double> r4(static_cast<size_t>(ncand) * 4), qh(static_cast<size_t>(ncand));
+        TBH_HIP(hipMemcpyAsync(r4.data(), res4, r4.size() * 8, hipMemcpyDeviceToHost, st));
+        TBH_HIP(hipMemcpyAsync(qh.data(), q.p, qh.size() * 8, hipMemcpyDeviceToHost, st));
+        TBH_HIP(hipStreamSynchronize(st));
+        std::vector<int> cb;
+        for (int c = 0; c < ncand; ++c) {
+            const double r = r4[size_t(4 * c + 1)], E = r4[size_t(4 * c + 2)], yn = r4[size_t(4 * c + 3)];
+            if (r <= res_tol_fill && E - qh[size_t(c)] / (yn * yn) > opt.sigma_mid) cb.push_back(c);
+        }
+        std::stable_sort(cb.begin(), cb.end(),
+                         [&](int x, int y) { return r4[size_t(4 * x + 2)] < r4[size_t(4 * y + 2)]; });
+        if (int(cb.size()) > opt.newton_states) cb.resize(size_t(opt.newton_states));
+        NewtonIn ni;
+        ni.Y = Ys;
+        ni.ns = int64_t(ns);
+        ni.n_o = h->n_o;
+        ni.n_atoms = h->n;
+        ni.node = node_d.as<int64_t>();
+        for (int a = 0; a < 3; ++a) ni.grid[a] = grid[a];
+        ni.h = opt.h_nm;
+        ni.kappa = scale;
+        ni.b = b.as<double>();
+        ni.sel = cb;
+        for (int c : cb) {
+            ni.E.push_back(r4[size_t(4 * c + 2)]);
+            ni.inv_norm.push_back(1.0 / r4[size_t(4 * c + 3)]);
+        }
+        ni.Ef = o[0];
+        ni.kT = opt.newton_kT;
+        ni.fixed = use_fixed != 0;
+        ni.cg_tol = opt.newton_cg_tol;
+        ni.cg_max_iter = opt.newton_cg_max_iter;
+        ni.depth = opt.anderson_depth;
+        NewtonOut no;
+        newton_update(st, nw, ni, U.as<double>(), &no);
+        rep.newton_cg_iters = no.cg_iters;
+        rep.newton_pairs = no.npairs;
+        rep.newton_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - tn).count();
+        // phi guess for the next Poisson solve: -U
+        hipLaunchKernelGGL(k_scale, dim3(gn), dim3(TPB), 0, st, n_nodes, U.as<double>(), -1.0, phi.as<double>());
+        TBH_HIP(hipGetLastError());
+    }
     ++iterations;
     have_prev = o[1] > 0;
     prev_emin = o[6];
@@ -747,7 +838,7 @@ void Scf::step(tbh_scf_report& rep) {
     prev_res = o[4];
     rep.iterations = iterations;
     rep.residual = o[4];
-    rep.converged = o[4] < opt.tol_eV;
+    rep.converged = o[4] < opt.tol_eV && neutral_ok;
     rep.fermi = o[0];
     rep.n_cb = int(o[1]);
     rep.n_conv = int(o[2]);

@@ -112,10 +112,10 @@ class Study:
                                                                       multi_vector=multi))
         self.torch = torch
 
-    def scf(self, seed):
+    def scf(self, seed, **over):
         p = self.problem(seed)
         s = tbh.SCF(self.ham, self.grid, p.extra["donor_atoms"], p.v0, self.gap["mid"], self.gap["cbm"],
-                    W.H_GRID_NM, **self.kw)
+                    W.H_GRID_NM, **{**self.kw, **over})
         return s, p
 
     def donor_map(self, p):
@@ -159,15 +159,16 @@ class Study:
     def surrogate(self, weights):
         return Start(self, weights)
 
-    def run(self, seed, start=None, max_iter=400, first_res_limit=0.0, mean_only=False, fixed_start=None):
+    def run(self, seed, start=None, max_iter=400, first_res_limit=0.0, mean_only=False, fixed_start=None, **over):
         """SCF of one layout from the zero start (start None), the mean start
         (start and mean_only) or the learned start (start), the start built
         by the library (tbh_scf_set_start, its time included), or from an
         explicit FP32 device map added to U_bare as the mean start
-        (fixed_start: a test of the fallback).  Returns the record
+        (fixed_start: a test of the fallback); over: loop options that
+        replace the geometry's (e.g. update_mode=1).  Returns the record
         (iterations, seconds, residuals, converged, fell_back, U, U0)."""
         torch = self.torch
-        s, p = self.scf(seed)
+        s, p = self.scf(seed, **over)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if fixed_start is not None:
@@ -379,12 +380,13 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
     return hist
 
 
-def evaluate(weights, seeds, max_iter=400, ctx=None, with_mean=True, geometry="study"):
+def evaluate(weights, seeds, max_iter=400, ctx=None, with_mean=True, geometry="study", newton=False):
     """Per held-out layout: SCF from the zero start, from the mean start (the
     network's output replaced by zero: the symmetrized training mean plus
     the bare-donor potential) and from the learned start, each start built
     by the library with its time included; the fallback limit is ten times
-    the zero start's first residual."""
+    the zero start's first residual.  newton: also the zero and learned
+    starts with the Newton-Raphson update in place of linear mixing."""
     st = Study(ctx, geometry=geometry)
     start = st.surrogate(weights)
     out = []
@@ -404,6 +406,11 @@ def evaluate(weights, seeds, max_iter=400, ctx=None, with_mean=True, geometry="s
                               start_seconds=learned["start_seconds"], converged=learned["converged"],
                               fell_back=learned["fell_back"], err0=float((learned["U0"] - Ustar).abs().max()),
                               fixed_point_diff=float((learned["U"] - Ustar).abs().max()))
+        if newton:
+            for kind, sta in (("zero_newton", None), ("learned_newton", start)):
+                r = st.run(sd, sta, max_iter, lim if sta is not None else 0.0, update_mode=1)
+                rec[kind] = dict(iterations=r["iterations"], seconds=r["seconds"], converged=r["converged"],
+                                 fell_back=r["fell_back"], fixed_point_diff=float((r["U"] - Ustar).abs().max()))
         out.append(rec)
         print(json.dumps(rec), flush=True)
     return out
@@ -419,6 +426,10 @@ def summarize(records):
              learned_err0=med("learned", "err0"),
              zero_err0=float(np.median([r["zero_err0"] for r in records])),
              fallbacks=int(sum(r["learned"]["fell_back"] for r in records)))
+    for kind in ("zero_newton", "learned_newton"):
+        if all(kind in r for r in records):
+            s[kind + "_iters"] = med(kind, "iterations")
+            s[kind + "_s"] = med(kind, "seconds")
     if all("mean" in r for r in records):
         s.update(mean_iters=med("mean", "iterations"), mean_s=med("mean", "seconds"),
                  mean_err0=med("mean", "err0"))
@@ -453,6 +464,7 @@ def main():
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="1000:1016")
     e.add_argument("--no-mean", action="store_true", help="skip the mean-start runs")
+    e.add_argument("--newton", action="store_true", help="also run both starts with the Newton-Raphson update")
     e.add_argument("--out", default=None)
     a = ap.parse_args()
     if a.cmd == "gen":
@@ -464,7 +476,7 @@ def main():
               dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight,
               geometry=a.geometry, time_budget=a.budget)
     else:
-        recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean, geometry=a.geometry)
+        recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean, geometry=a.geometry, newton=a.newton)
         s = summarize(recs)
         print(json.dumps(dict(summary=s)), flush=True)
         if a.out:

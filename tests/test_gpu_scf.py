@@ -147,3 +147,61 @@ def test_filtered_eigs_lowest_conduction_states(ctx):
     R = (H @ Y.T) - Y.T * r["evals"][None, :]
     assert np.linalg.norm(R, axis=0).max() < 1e-4
     assert np.abs(Y @ Y.T - np.eye(40)).max() < 1e-5
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+def test_newton_iterates_match_oracle(ctx, fixed):
+    """Newton-Raphson updates (Jacobian from the 64 lowest filled-class
+    states, occupations smeared at 10 meV inside it, Anderson depth 4) on the
+    small slab with the full Krylov space, against the oracle's dense Newton
+    loop from the same start: the potential iterate by iterate to 1e-8 eV."""
+    import torch
+    from oracle import newton as NW
+    p, grid, U0 = _slab()
+    ge = p.extra["gap"]
+    donors = p.extra["donor_atoms"]
+    nit = 5
+    ef = ge["cbm"] - 0.3 if fixed else None
+    ro = NW.scf_newton(p, donors, grid, U0, ge["mid"], tol=1e-12, max_iter=nit, Ef_fixed=ef, n_states=64,
+                       kT_J=0.01, depth=4)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64"))
+    dim = p.dim
+    scf = tbh.SCF(h, grid, donors, p.v0, ge["mid"], ge["cbm"], W.H_GRID_NM, tol_eV=1e-12, n_cand=dim,
+                  lanczos_iter=dim, res_tol=1e-6, fermi_fixed=ef, update_mode=1, newton_states=64, newton_kT=0.01,
+                  anderson_depth=4, newton_cg_tol=1e-13)
+    scf.set_potential(torch.tensor(U0).cuda())
+    for t in range(nit):
+        Ug = scf.potential().cpu().numpy()
+        err = np.abs(Ug - ro["iterates"][t]).max()
+        r = scf.step()
+        print(f"iter {t} |dU|={err:.3e} res gpu {r['residual']:.6e} oracle {ro['residuals'][t]:.6e} "
+              f"pairs {r['newton_pairs']} cg {r['newton_cg_iters']}", flush=True)
+        assert err < 1e-8
+        assert abs(r["residual"] - ro["residuals"][t]) < 1e-8
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["lanczos_cgs2", "filtered_block"])
+def test_newton_production_setting_is_an_oracle_fixed_point(ctx, mode):
+    """The study slab in the production setting with the Newton-Raphson
+    update: converges in at most 40 steps (linear mixing needs about 190),
+    and the converged potential is a fixed point of one dense FP64 oracle
+    step (|U_out - U| < 1e-4 eV at every node)."""
+    p = W.study_slab(1003)
+    ge = p.extra["gap"]
+    grid = p.extra["grid"]
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f32", keep_f64=True, multi_vector=(mode == 1)))
+    kw = dict(mix_alpha=0.05, tol_eV=1e-4, res_tol=1e-4, T_K=4.0, update_mode=1)
+    if mode == 0:
+        kw.update(n_cand=64, lanczos_iter=800)
+    else:
+        kw.update(eig_mode=1, block=64, filter_degree=20, filter_degree_cold=80, filter_max_iter=60, k_states=40,
+                  e_vbm=ge["vbm"])
+    scf = tbh.SCF(h, grid, p.extra["donor_atoms"], p.v0, ge["mid"], ge["cbm"], W.H_GRID_NM, **kw)
+    r = scf.run(100)
+    print(f"newton mode {mode}: steps {r['iterations']} residual {r['residual']:.2e} seconds {r['seconds']:.2f}",
+          flush=True)
+    assert r["converged"] and r["iterations"] <= 40
+    U = scf.potential().cpu().numpy()
+    d = np.abs(_dense_step(p, grid, U) - U).max()
+    print(f"dense oracle step from the GPU's U: max |U_out - U| = {d:.2e} eV", flush=True)
+    assert d < 1e-4
