@@ -140,7 +140,8 @@ def scf_leg(seeds, max_iter=600):
     """SCF time-to-converge on the 8x8x60-cell delta-doped slab (30,720
     atoms, 64 donors, 4 K, linear mixing 0.05 to 1e-4 eV): the zero start
     against the learned start (the committed network, built on the device by
-    tbh_scf_set_start, its time included), on held-out donor layouts."""
+    tbh_scf_set_start, its time included), on held-out donor layouts; and, as
+    context, the zero start with the Newton-Raphson update."""
     import paper_1003_4570_amd as tbh
     from paper_1003_4570_amd import surrogate as S
     weights = os.path.join(ROOT, "paper_1003_4570_amd", "data", "surrogate_c5.npz")
@@ -154,7 +155,11 @@ def scf_leg(seeds, max_iter=600):
         zero = st.run(sd, None, max_iter)
         print(f"bench: SCF layout {sd}, learned start", file=sys.stderr, flush=True)
         learned = st.run(sd, start, max_iter, 10.0 * zero["residuals"][0])
+        print(f"bench: SCF layout {sd}, zero start, Newton-Raphson update", file=sys.stderr, flush=True)
+        newton = st.run(sd, None, max_iter, update_mode=1)
         recs.append(dict(seed=sd, zero_iterations=zero["iterations"], zero_seconds=round(zero["seconds"], 3),
+                         newton_zero_iterations=newton["iterations"], newton_zero_seconds=round(newton["seconds"], 3),
+                         newton_zero_converged=newton["converged"],
                          zero_converged=zero["converged"], learned_iterations=learned["iterations"],
                          learned_seconds=round(learned["seconds"], 3),
                          learned_start_seconds=round(learned["start_seconds"], 4),
@@ -167,7 +172,10 @@ def scf_leg(seeds, max_iter=600):
     return dict(workload="scf_c5_slab8x8x60_sp3d5s_64donors_4K", measured="in this run",
                 held_out_seeds=list(seeds), zero_seconds=zs, learned_seconds=ls, zero_iterations=zi,
                 learned_iterations=li, speedup_time=round(zs / ls, 3), speedup_iterations=round(zi / li, 3),
-                tolerance_eV=1e-4, records=recs)
+                tolerance_eV=1e-4,
+                newton_zero_seconds=float(np.median([r["newton_zero_seconds"] for r in recs])),
+                newton_zero_iterations=float(np.median([r["newton_zero_iterations"] for r in recs])),
+                records=recs)
 
 
 def calibrate_copy():
@@ -267,7 +275,12 @@ def bench_c4(a):
         Ys.append(torch.empty_like(Xs[-1]))
         atoms += prob.n_atoms
     b = tbh.Batch(ctx, hams, Xs, Ys)
-    cfg = b.autotune(None)
+    if a.c4_grid > 0:
+        # a fixed configuration: the trace then holds the batched launches alone
+        b.configure(a.c4_grid, a.c4_remap)
+        cfg = dict(grid=a.c4_grid, remap=a.c4_remap, ms=None)
+    else:
+        cfg = b.autotune(None)
 
     def timeit(fn, reps=10):
         fn()
@@ -281,7 +294,7 @@ def bench_c4(a):
         return e0.elapsed_time(e1) / reps
 
     t_graph = timeit(b.apply)
-    t_sep = timeit(b.apply_separate)
+    t_sep = None if a.c4_batched_only else timeit(b.apply_separate)
     per_atom = 5 * 10 * 10 * 8 + 16 + 2 * 10 * 16 * 8
     byts = per_atom * atoms
     flops = atoms * 2 * (5 * 10 * 10) * 16 * 4     # complex MACs: 4 real multiply-adds
@@ -289,9 +302,97 @@ def bench_c4(a):
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32",
            "config": {"workload": "c4_48cells_x4k_sp3s_so_16rhs", "atom_k_instances": atoms,
                       "bytes_per_apply": byts},
-           "extra": dict(ms_graph=t_graph, ms_separate=t_sep, speedup_vs_separate=t_sep / t_graph,
+           "extra": dict(ms_graph=t_graph, ms_separate=t_sep,
+                         speedup_vs_separate=None if t_sep is None else t_sep / t_graph,
                          autotuned=cfg, tflops=flops / t_graph / 1e9,
                          mfma_fp32_frac=flops / t_graph / 1e9 / 157.3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_c2sd(a):
+    """The 64,000-atom hard-wall SO cube (C2) with spin-diagonal bond storage
+    against the stored format: time per fused H.x of 500 Lanczos steps
+    (HIP events), the bytes each format reads, and the 16 values nearest
+    mid-gap of the full 6000-step solve through each format."""
+    import torch
+    import paper_1003_4570_amd as tbh
+    import workloads as W
+    prob = W.c2_hardwall_so(0, m=a.c2_m)
+    ctx = tbh.Context(0)
+    v0 = torch.tensor(np.ascontiguousarray(prob.v0).view(np.float64), device="cuda")
+    res = {}
+    for fmt in ("stored", "spin_diagonal"):
+        print(f"bench c2sd: build {fmt}", file=sys.stderr, flush=True)
+        ham = tbh.build_hamiltonian(ctx, **tbh.problem_args(prob, keep_f64=True,
+                                                           spin_diagonal=(fmt == "spin_diagonal")))
+        tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            a_, b_, _ = tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False)
+        torch.cuda.synchronize()
+        step_us = (time.perf_counter() - t0) / (3 * ITERS_PER_STEP) * 1e6
+        _, _, rep = tbh.lanczos_run(ham, ITERS_PER_STEP, v0, reorth=False, time_hx=True)
+        hx_us = rep["hx_seconds"] / ITERS_PER_STEP * 1e6
+        by = ham.info["hx_bytes"] + ham.info["dim"] * 8          # + x_prev (complex FP32)
+        print(f"bench c2sd: solve {fmt}", file=sys.stderr, flush=True)
+        r = tbh.lanczos_eigs(ham, prob.sigma, 16, a.c2_m, v0, reorth=False, n_cand=a.c2_cand)
+        res[fmt] = dict(hx_us=hx_us, step_us=step_us, hx_bytes=by, GBs=by / (hx_us * 1e-6) / 1e9, alpha=a_,
+                        refined=np.sort(r["refined"]), n_found=r["report"]["n_found"],
+                        solve_s=r["report"]["seconds"])
+        del ham
+        torch.cuda.empty_cache()
+    st, sd = res["stored"], res["spin_diagonal"]
+    diff = float(np.abs(st["refined"] - sd["refined"]).max()) if st["n_found"] == sd["n_found"] else None
+    out = {"metric": "H.x time per Lanczos step, spin-diagonal bond blocks", "value": round(sd["hx_us"], 2),
+           "unit": "us", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": f"lanczos{a.c2_m}_si20x20x20_hardwall_sp3d5s_so_spin_diagonal",
+                      "atoms": prob.n_atoms},
+           "extra": {"stored_hx_us": round(st["hx_us"], 2), "hx_speedup": round(st["hx_us"] / sd["hx_us"], 2),
+                     "stored_step_us": round(st["step_us"], 2), "spin_diagonal_step_us": round(sd["step_us"], 2),
+                     "stored_hx_bytes": st["hx_bytes"], "spin_diagonal_hx_bytes": sd["hx_bytes"],
+                     "stored_GBs": round(st["GBs"], 1), "spin_diagonal_GBs": round(sd["GBs"], 1),
+                     "spin_diagonal_frac_hbm": round(sd["GBs"] / 8000.0, 4),
+                     "stored_solve_s": round(st["solve_s"], 3), "spin_diagonal_solve_s": round(sd["solve_s"], 3),
+                     "n_found": [st["n_found"], sd["n_found"]], "max_refined_diff_eV": diff,
+                     "max_alpha_diff_vs_stored": float(abs(st["alpha"][:50] - sd["alpha"][:50]).max())}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_c5train(a):
+    """Training step of the start-potential surrogate on the 8x8x60-cell
+    slab's grid (32 x 32 x 240 nodes, 4 input maps, 6 layers of 32 channels,
+    dilations 1,2,4,8,2,1), batch 8 of seeded random maps: time per sample
+    and the convolutions' MFMA rate (forward, backward-data and weight
+    gradient: 3 x 2 x 27 x C_in x C_out flop per voxel and layer) against
+    the FP16 dense peak."""
+    import torch
+    import paper_1003_4570_amd as tbh
+    import workloads as W
+    grid = (32, 32, 240)
+    nx, ny, nz = grid
+    dil = (1, 2, 4, 8, 2, 1)
+    ctx = tbh.Context(0)
+    net = tbh.Net(ctx, grid, in_channels=4, dilations=dil)
+    net.set_params(W.init_surrogate_weights(0, in_channels=4, n_layers=len(dil)))
+    g = torch.Generator(device="cpu").manual_seed(0)
+    xs = [torch.randn((4, nz, ny, nx), generator=g).float().cuda() for _ in range(8)]
+    ts = [torch.randn((nz, ny, nx), generator=g).float().cuda() for _ in range(8)]
+    for _ in range(max(1, a.warmup)):
+        net.train_step(xs, ts, lr=1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        net.train_step(xs, ts, lr=1e-5)
+    torch.cuda.synchronize()
+    per_sample = (time.perf_counter() - t0) / (a.steps * len(xs))
+    chans = [(4, 32)] + [(32, 32)] * (len(dil) - 2) + [(32, 1)]
+    flops = 3 * 2 * 27 * sum(ci * co for ci, co in chans) * nx * ny * nz
+    out = {"metric": "surrogate training time per sample", "value": round(per_sample * 1e3, 3), "unit": "ms",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f16 (f32 accumulation)",
+           "config": {"workload": "surrogate_train_grid32x32x240_6layers_32ch_batch8"},
+           "extra": {"conv_tflops": round(flops / per_sample / 1e12, 2),
+                     "mfma_fp16_frac": round(flops / per_sample / 1e12 / 2500.0, 4)}}
     print(json.dumps(out), flush=True)
 
 
@@ -344,11 +445,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c3t"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c3t", "c2sd", "c5train"],
                     help="c3: H.x GB/s in Lanczos (default); c2: FP32 vs FP64 eigenvalues; "
-                         "c4: batched multi-vector H.X; c3t: the c3 alloy with tabulated bond blocks")
+                         "c4: batched multi-vector H.X; c3t: the c3 alloy with tabulated bond blocks; "
+                         "c2sd: c2 with spin-diagonal bond blocks; c5train: surrogate training step")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF learned-vs-zero-start leg")
     ap.add_argument("--scf-layouts", type=int, default=2, help="held-out donor layouts of the SCF leg")
+    ap.add_argument("--c4-grid", type=int, default=0, help="c4: fixed persistent grid (0 = autotune)")
+    ap.add_argument("--c4-remap", type=int, default=2, help="c4: atom walk with --c4-grid (0, 1 or 2)")
+    ap.add_argument("--c4-batched-only", action="store_true", help="c4: skip the one-launch-per-cell timing")
     ap.add_argument("--c2-m", type=int, default=6000)
     ap.add_argument("--c2-cand", type=int, default=256)
     a = ap.parse_args()
@@ -364,6 +469,12 @@ def main():
         return
     if a.workload == "c4":
         bench_c4(a)
+        return
+    if a.workload == "c5train":
+        bench_c5train(a)
+        return
+    if a.workload == "c2sd":
+        bench_c2sd(a)
         return
     if a.workload == "c3t":
         bench_c3t(a)

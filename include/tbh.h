@@ -153,6 +153,16 @@ typedef struct {
      * returns TBH_EINVAL otherwise.  onsite_pot becomes the ham's per-atom
      * potential (as tbh_ham_set_potential). */
     int32_t tabulated;
+    /* 1: spin-diagonal bond storage for an H with spin at Gamma.  Hopping is
+     * spin-independent in the two-centre form (Sec. I; the spin-orbit term of
+     * the sp3d5s*+SO model sits on the atom), so every bond block is
+     * I_2 (x) b with b real (n_o/2 x n_o/2, strain scale included): the
+     * packed H keeps b once per bond and the full complex on-site block
+     * (passivation and spin-orbit).  For sp3d5s*+SO in FP32 that is 4,800 B
+     * per atom instead of 16,000.  Needs spin, Gamma (no kfrac), no
+     * tabulated, lanes_per_atom 0; the build checks every bond block for the
+     * I_2 (x) real form and returns TBH_EINVAL otherwise. */
+    int32_t spin_diagonal;
 } tbh_build_opts;
 
 typedef struct {
@@ -170,6 +180,7 @@ typedef struct {
                                  key records + block table) + neighbour
                                  table + x once + y once (+ potential) */
     int32_t tabulated;        /* 1 if the bond blocks are tabulated */
+    int32_t spin_diagonal;    /* 1 if the bond blocks are stored spin-diagonal */
 } tbh_ham_info;
 
 /* Pure host step of the build: neighbour table and the assembled FP64
@@ -592,8 +603,11 @@ typedef struct tbh_batch tbh_batch;
 /* hams[count] (same orbital count and complex-ness, TBH_F32, multi_vector),
  * X[count], Y[count]: device buffers as in tbh_apply_h_multi.  The batch
  * keeps the pointers (which must stay valid) and a captured graph of the
- * launch.  grid / remap: persistent workgroups and XCD-contiguous mapping
- * (0 = defaults: 8 workgroups per CU, remap on). */
+ * launch.  grid / remap: persistent workgroups and their walk over the
+ * concatenated atoms (defaults: 8 workgroups per CU, remap 1): remap 0 = one
+ * grid-wide window of consecutive atoms in workgroup order; 1 = the same
+ * window with each XCD holding a contiguous part of it; 2 = each XCD owns a
+ * contiguous eighth of the atoms, swept by its own workgroups. */
 int tbh_batch_create(tbh_ctx* ctx, tbh_ham* const* hams, int32_t count, const float* const* X, float* const* Y,
                      int32_t nrhs, tbh_batch** out);
 int tbh_batch_destroy(tbh_batch* b);
@@ -642,7 +656,11 @@ int tbh_net_set_loss_weights(tbh_net* n, const float* w_dev);
  * canonical order) and the loss. */
 int tbh_net_gradients(tbh_net* n, const float* x_dev, const float* t_dev, float* grad, double* loss);
 /* One Adam step on the mean loss over a batch of (x[i], t[i]) device maps;
- * loss = mean over the batch before the step. */
+ * loss = mean over the batch before the step.  When the loss or any
+ * gradient entry is not finite (an overflow of the half-precision
+ * activations or their gradients) the step is skipped: weights, moments and
+ * the step count stay as they were, and loss reports the non-finite value
+ * or the loss of the skipped batch. */
 int tbh_net_train_step(tbh_net* n, const float* const* x_dev, const float* const* t_dev, int32_t batch,
                        double lr, double* loss);
 

@@ -47,7 +47,7 @@ class tbh_build_opts(C.Structure):
     _fields_ = [("bond_scale", C.POINTER(C.c_double)), ("onsite_pot", C.POINTER(C.c_double)),
                 ("kfrac", C.POINTER(C.c_double)), ("prec", C.c_int32),
                 ("lanes_per_atom", C.c_int32), ("keep_f64", C.c_int32),
-                ("multi_vector", C.c_int32), ("tabulated", C.c_int32)]
+                ("multi_vector", C.c_int32), ("tabulated", C.c_int32), ("spin_diagonal", C.c_int32)]
 
 
 class tbh_ham_info(C.Structure):
@@ -55,7 +55,7 @@ class tbh_ham_info(C.Structure):
                 ("is_complex", C.c_int32), ("prec", C.c_int32), ("lanes_per_atom", C.c_int32),
                 ("onsite_diagonal", C.c_int32), ("has_f64", C.c_int32),
                 ("n_dangling", C.c_int64), ("stored_bytes", C.c_int64), ("hx_bytes", C.c_int64),
-                ("tabulated", C.c_int32)]
+                ("tabulated", C.c_int32), ("spin_diagonal", C.c_int32)]
 
 
 class tbh_lanczos_opts(C.Structure):
@@ -239,7 +239,7 @@ class _Inputs:
     def __init__(self, pos_q, species, box_q, periodic, model, spin, onsite, sk,
                  so_delta=None, passivation_eV=0.0, bond_scale=None, onsite_pot=None,
                  kfrac=None, prec=TBH_F32, lanes_per_atom=0, keep_f64=False, n_species=None,
-                 multi_vector=False, tabulated=False):
+                 multi_vector=False, tabulated=False, spin_diagonal=False):
         self.pos = _dptr(pos_q, np.int32).reshape(-1, 3)
         self.spc = _dptr(species, np.uint8).ravel()
         self.onsite = _dptr(onsite, np.float64)
@@ -258,7 +258,8 @@ class _Inputs:
                               _p(self.sk, C.c_double), _p(self.so, C.c_double), float(passivation_eV))
         self.opt = tbh_build_opts(_p(self.bs, C.c_double), _p(self.pot, C.c_double),
                                   _p(self.kf, C.c_double), int(prec), int(lanes_per_atom),
-                                  int(bool(keep_f64)), int(bool(multi_vector)), int(bool(tabulated)))
+                                  int(bool(keep_f64)), int(bool(multi_vector)), int(bool(tabulated)),
+                                  int(bool(spin_diagonal)))
         self.n = self.pos.shape[0]
         self.n_o = (5 if int(model) == TBH_SP3S else 10) * (2 if spin else 1)
 

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <exception>
 #include <thread>
 
 #include "tbh_internal.h"
@@ -328,11 +329,86 @@ Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool 
     return L;
 }
 
+Layout make_layout_sd(int64_t n_atoms, int n_o, int prec, int R) {
+    Layout L;
+    const int nb = n_o / 2;
+    L.sd = true;
+    L.n_o = n_o;
+    L.R = R;
+    L.G = nb / R;
+    L.A = 64 / L.G;
+    L.L = L.A * L.G;
+    L.cs = 2;
+    L.esz = prec == TBH_F64 ? 8 : 4;
+    L.K = 16 / L.esz;
+    L.bond_chunks = (R * nb + L.K - 1) / L.K;
+    L.onsite_chunks = (2 * R * n_o * 2 + L.K - 1) / L.K;
+    L.C = 4 * L.bond_chunks + L.onsite_chunks;
+    L.diag = false;
+    L.n_tiles = (n_atoms + L.A - 1) / L.A;
+    L.bytes = L.n_tiles * int64_t(L.C) * L.L * 16;
+    return L;
+}
+
 namespace {
+
+// spin-diagonal packing: per bond the real orbital block b of I_2 (x) b, then
+// the full complex on-site rows of both spins; every bond block is checked
+// for that form
+template <typename T>
+void pack_range_sd(const HostModel& M, const Layout& L, T* dst, int64_t t0, int64_t t1, const int64_t* perm) {
+    const int no = M.n_o, nb = no / 2;
+    std::vector<cplx> D(no * no), B(4 * no * no);
+    for (int64_t t = t0; t < t1; ++t) {
+        for (int la = 0; la < L.A; ++la) {
+            const int64_t a = t * L.A + la;
+            const bool live = a < M.n;
+            if (live) {
+                host_atom_blocks(M, perm ? perm[a] : a, D.data(), B.data());
+                for (int b = 0; b < 4; ++b)
+                    for (int r = 0; r < no; ++r)
+                        for (int c = 0; c < no; ++c) {
+                            const cplx v = B[(size_t(b) * no + r) * no + c];
+                            const cplx want = (r / nb == c / nb) ? B[(size_t(b) * no + r % nb) * no + c % nb] : 0.0;
+                            TBH_REQUIRE(v.imag() == 0.0 && v == want,
+                                        "spin-diagonal storage needs every bond block to be I_2 (x) a real block");
+                        }
+            }
+            for (int g = 0; g < L.G; ++g) {
+                const int lane = la * L.G + g;
+                auto put = [&](int s, double v) {
+                    const int c = s / L.K, e = s % L.K;
+                    dst[((t * L.C + c) * L.L + lane) * L.K + e] = live ? T(v) : T(0);
+                };
+                for (int b = 0; b < 4; ++b) {
+                    const int base = b * L.bond_chunks * L.K;
+                    int s = 0;
+                    for (int r = 0; r < L.R; ++r)
+                        for (int c = 0; c < nb; ++c) put(base + s++, B[(size_t(b) * no + g * L.R + r) * no + c].real());
+                    while (s < L.bond_chunks * L.K) put(base + s++, 0.0);
+                }
+                const int base = 4 * L.bond_chunks * L.K;
+                int s = 0;
+                for (int sp = 0; sp < 2; ++sp)
+                    for (int r = 0; r < L.R; ++r)
+                        for (int c = 0; c < no; ++c) {
+                            const cplx v = D[(sp * nb + g * L.R + r) * no + c];
+                            put(base + s++, v.real());
+                            put(base + s++, v.imag());
+                        }
+                while (s < L.onsite_chunks * L.K) put(base + s++, 0.0);
+            }
+        }
+    }
+}
 
 template <typename T>
 void pack_range(const HostModel& M, const Layout& L, bool diag, T* dst, int64_t t0, int64_t t1,
                 const int64_t* perm) {
+    if (L.sd) {
+        pack_range_sd(M, L, dst, t0, t1, perm);
+        return;
+    }
     const int no = M.n_o;
     std::vector<cplx> D(no * no), B(4 * no * no);
     for (int64_t t = t0; t < t1; ++t) {
@@ -565,18 +641,24 @@ void pack_layout(const HostModel& M, const Layout& L, bool diag, void* dst, cons
     nt = nt == 0 ? 1 : (nt > 16 ? 16 : nt);
     if (L.n_tiles < 64) nt = 1;
     std::vector<std::thread> th;
+    // a worker's error (a block that does not fit the layout) is rethrown here
+    std::vector<std::exception_ptr> err(nt);
     const int64_t per = (L.n_tiles + nt - 1) / nt;
     for (unsigned w = 0; w < nt; ++w) {
         const int64_t t0 = w * per, t1 = std::min<int64_t>(L.n_tiles, t0 + per);
         if (t0 >= t1) break;
-        if (L.esz == 8)
-            th.emplace_back(pack_range<double>, std::cref(M), std::cref(L), diag,
-                            static_cast<double*>(dst), t0, t1, perm);
-        else
-            th.emplace_back(pack_range<float>, std::cref(M), std::cref(L), diag,
-                            static_cast<float*>(dst), t0, t1, perm);
+        th.emplace_back([&, w, t0, t1] {
+            try {
+                if (L.esz == 8) pack_range<double>(M, L, diag, static_cast<double*>(dst), t0, t1, perm);
+                else pack_range<float>(M, L, diag, static_cast<float*>(dst), t0, t1, perm);
+            } catch (...) {
+                err[w] = std::current_exception();
+            }
+        });
     }
     for (auto& t : th) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 }  // namespace tbh

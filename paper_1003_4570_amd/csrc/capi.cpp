@@ -227,6 +227,7 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
         // add pot[i] x_i, so tbh_ham_set_potential replaces it (NULL = 0).
         std::vector<double> pot0;
         pot0.swap(M.pot);
+        TBH_REQUIRE(!(o->tabulated && o->spin_diagonal), "tabulated and spin_diagonal exclude each other");
         if (o->tabulated) {
             TBH_REQUIRE(!o->multi_vector, "tabulated blocks do not combine with multi_vector");
             TBH_REQUIRE(o->lanes_per_atom == 0 || o->lanes_per_atom == 1, "tabulated blocks use one lane per atom");
@@ -272,6 +273,30 @@ int tbh_build_hamiltonian(tbh_ctx* ctx, const tbh_geometry* g, const tbh_params*
             if (o->prec == TBH_F32 && o->keep_f64) {
                 h->lay64 = tab_layout(TBH_F64);
                 upload(h->blocks64, TBH_F64);
+                h->has_f64 = true;
+            } else if (o->prec == TBH_F64) {
+                h->has_f64 = true;
+            }
+        } else if (o->spin_diagonal) {
+            TBH_REQUIRE(M.spin, "spin_diagonal needs a model with spin");
+            TBH_REQUIRE(!o->kfrac || (o->kfrac[0] == 0.0 && o->kfrac[1] == 0.0 && o->kfrac[2] == 0.0),
+                        "spin_diagonal needs Gamma (a Bloch phase makes the bond blocks complex)");
+            TBH_REQUIRE(o->lanes_per_atom == 0, "spin_diagonal chooses its own lanes per atom");
+            // lanes own R orbitals in both spins: 2 of 10 (sp3d5s*) or 1 of 5 (sp3s*)
+            const int R = M.n_o == 20 ? 2 : 1;
+            h->lay = tbh::make_layout_sd(M.n, M.n_o, o->prec, R);
+            {
+                std::vector<char> host(size_t(h->lay.bytes));
+                tbh::pack_layout(M, h->lay, false, host.data(), perm);
+                h->blocks.alloc(host.size());
+                TBH_HIP(hipMemcpy(h->blocks.p, host.data(), host.size(), hipMemcpyHostToDevice));
+            }
+            if (o->prec == TBH_F32 && o->keep_f64) {
+                h->lay64 = tbh::make_layout_sd(M.n, M.n_o, TBH_F64, R);
+                std::vector<char> host(size_t(h->lay64.bytes));
+                tbh::pack_layout(M, h->lay64, false, host.data(), perm);
+                h->blocks64.alloc(host.size());
+                TBH_HIP(hipMemcpy(h->blocks64.p, host.data(), host.size(), hipMemcpyHostToDevice));
                 h->has_f64 = true;
             } else if (o->prec == TBH_F64) {
                 h->has_f64 = true;
@@ -354,6 +379,7 @@ int tbh_ham_info_get(const tbh_ham* h, tbh_ham_info* out) {
         out->stored_bytes = h->lay.bytes;
         out->hx_bytes = h->hx_bytes();
         out->tabulated = h->lay.tab;
+        out->spin_diagonal = h->lay.sd;
     });
 }
 

@@ -177,7 +177,7 @@ int tbh_batch_apply_separate(tbh_batch* b) {
 
 int tbh_batch_configure(tbh_batch* b, int32_t grid, int32_t remap) {
     return guard([&] {
-        TBH_REQUIRE(b && grid >= 1 && (remap == 0 || remap == 1), "bad configuration");
+        TBH_REQUIRE(b && grid >= 1 && remap >= 0 && remap <= 2, "bad configuration");
         TBH_HIP(hipSetDevice(b->ctx->device));
         b->grid = grid;
         b->remap = remap;
@@ -215,7 +215,7 @@ int tbh_batch_autotune(tbh_batch* b, const char* cache_path, int32_t* grid_out, 
             double best = 1e30;
             int bg = b->grid, br = b->remap;
             for (int per_cu : {2, 4, 8, 16, 32}) {
-                for (int rm : {0, 1}) {
+                for (int rm : {0, 1, 2}) {
                     b->grid = int(std::min<int64_t>(int64_t(per_cu) * cus, b->total));
                     b->remap = rm;
                     const double ms = time_ms(b, 3);

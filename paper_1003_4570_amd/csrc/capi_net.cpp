@@ -1,4 +1,5 @@
 // C ABI: the convolutional surrogate (inference, gradients, training step).
+#include <cmath>
 #include <vector>
 
 #include "conv.h"
@@ -149,7 +150,8 @@ int tbh_net_train_step(tbh_net* n, const float* const* x_dev, const float* const
             TBH_REQUIRE(x_dev[b] && t_dev[b], "null sample");
             tot += n->accumulate_gradients(x_dev[b], t_dev[b]);
         }
-        n->adam(lr, batch);
+        // a non-finite loss or gradient (half-precision overflow) skips the update
+        if (std::isfinite(tot)) (void)n->adam(lr, batch);
         if (loss) *loss = tot / batch;
     });
 }

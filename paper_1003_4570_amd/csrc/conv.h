@@ -17,7 +17,7 @@ struct Net {
     int64_t n_params = 0;
     int64_t off_w[MAX_LAYERS], off_b[MAX_LAYERS];
     int lin[MAX_LAYERS], lout[MAX_LAYERS];
-    DevBuf w32, m32, v32, grad, w16, wt16, xin, pred, part, dpart, scalar, lw;
+    DevBuf w32, m32, v32, grad, w16, wt16, xin, pred, part, dpart, scalar, lw, counts;
     DevBuf act[MAX_LAYERS], dact[2];   // act[l]: output of layer l < L-1 (FP16)
     bool weighted = false;             // lw holds per-voxel loss weights
     int nchunk = 1;
@@ -29,7 +29,7 @@ struct Net {
     void forward(const float* x_dev, float* y_dev);      // x: [CI][nvox]; y_dev null: into pred
     double accumulate_gradients(const float* x_dev, const float* t_dev);  // returns the sample's MSE
     void zero_grad();
-    void adam(double lr, int batch);
+    bool adam(double lr, int batch);   // false: skipped (non-finite gradient)
 };
 
 }  // namespace tbh

@@ -22,6 +22,7 @@
 // gradient is scaled by the voxel count (sum of squares) so FP16 gradients
 // stay in range; the optimizer divides it back out.
 #include <cmath>
+#include <vector>
 
 #include "conv.h"
 #include "tbh_internal.h"
@@ -312,6 +313,19 @@ __global__ void k_adam(int64_t n, float* w, float* m, float* v, const float* gra
     }
 }
 
+// count of non-finite gradient entries (a half-precision overflow in the
+// backward pass shows up here as inf or NaN)
+__global__ void k_count_nonfinite(int64_t n, const float* g, int* count) {
+    int c = 0;
+    for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+        c += std::isfinite(g[i]) ? 0 : 1;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    __shared__ int sh[TPB / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) count[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
 __global__ void k_fill_f32(int64_t n, float* a, float val) {
     for (int64_t i = blockIdx.x * int64_t(TPB) + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) a[i] = val;
 }
@@ -387,6 +401,7 @@ Net::Net(Ctx* c, int channels, int in_channels, int n_layers, const int* dilatio
     part.alloc(size_t(nchunk) * (int64_t(C) * 27 * C + C) * 4);
     dpart.alloc(4096 * 8);
     scalar.alloc(8 * 8);
+    counts.alloc(64 * sizeof(int));
     step_t = 0;
     zero_moments();
 }
@@ -482,7 +497,17 @@ void Net::zero_grad() {
     hipLaunchKernelGGL(k_fill_f32, dim3(gfor(n_params)), dim3(TPB), 0, ctx->stream, n_params, grad.as<float>(), 0.f);
 }
 
-void Net::adam(double lr, int batch) {
+bool Net::adam(double lr, int batch) {
+    // a step with a non-finite gradient entry is skipped: weights and moments
+    // stay as they are
+    const int64_t gb = std::min<int64_t>(gfor(n_params), 64);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(gb), dim3(TPB), 0, ctx->stream, n_params, grad.as<float>(),
+                       counts.as<int>());
+    std::vector<int> cnt(static_cast<size_t>(gb));
+    TBH_HIP(hipMemcpyAsync(cnt.data(), counts.p, size_t(gb) * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    TBH_HIP(hipStreamSynchronize(ctx->stream));
+    for (int c : cnt)
+        if (c != 0) return false;
     ++step_t;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = 1.f - std::pow(b1, float(step_t)), c2 = 1.f - std::pow(b2, float(step_t));
@@ -492,6 +517,7 @@ void Net::adam(double lr, int batch) {
                        m32.as<float>(), v32.as<float>(), grad.as<float>(), w16.as<_Float16>(), gscale, float(lr),
                        b1, b2, eps, c1, c2);
     TBH_HIP(hipGetLastError());
+    return true;
 }
 
 }  // namespace tbh

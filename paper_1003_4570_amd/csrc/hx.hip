@@ -395,6 +395,195 @@ void launch_shape(const Layout& lay, const HxArgs& h, hipStream_t s) {
 
 
 // ---------------------------------------------------------------------------
+// Spin-diagonal bond blocks (H with spin at Gamma).  The two-centre hopping
+// does not act on spin, so every bond block is I_2 (x) b with b real
+// (NB x NB, NB = NO / 2); the spin-orbit term lives in the complex on-site
+// block.  A lane owns R orbitals in both spins (2R complex rows of y); its
+// stream holds, per bond, its R rows of b (R NB reals), then its 2R complex
+// on-site rows (spin up rows, then spin down).  Per bond it reads R NB
+// scalars instead of R NO complex ones (a quarter), and each b element
+// multiplies the neighbour's x in both spins.
+// ---------------------------------------------------------------------------
+template <typename T, int NB, int R, int C>
+__device__ __forceinline__ void consume_sd(const typename Vec16<T>::type& v, const T (&xv)[4][4 * NB],
+                                           const T (&xa)[4 * NB], T (&acc)[4 * R]) {
+    constexpr int NO = 2 * NB;
+    constexpr int K = 16 / sizeof(T);
+    constexpr int BC = (R * NB + K - 1) / K;
+    if constexpr (C < 4 * BC) {
+        constexpr int seg = C / BC, cc = C % BC;
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            const int s = cc * K + e;
+            if (s < R * NB) {
+                const int r = s / NB, c = s % NB;
+                const T b = v[e];
+#pragma unroll
+                for (int sp = 0; sp < 2; ++sp) {
+                    acc[(sp * R + r) * 2] = fma(b, xv[seg][(sp * NB + c) * 2], acc[(sp * R + r) * 2]);
+                    acc[(sp * R + r) * 2 + 1] = fma(b, xv[seg][(sp * NB + c) * 2 + 1], acc[(sp * R + r) * 2 + 1]);
+                }
+            }
+        }
+    } else {
+        constexpr int cc = C - 4 * BC;
+#pragma unroll
+        for (int e = 0; e < K; e += 2) {
+            const int s = cc * K + e;
+            if (s < 2 * R * NO * 2) {
+                const int el = s / 2, row = el / NO, col = el % NO;
+                const T br = v[e], bi = v[e + 1];
+                const T xr = xa[2 * col], xi = xa[2 * col + 1];
+                acc[2 * row] = fma(br, xr, acc[2 * row]);
+                acc[2 * row] = fma(-bi, xi, acc[2 * row]);
+                acc[2 * row + 1] = fma(br, xi, acc[2 * row + 1]);
+                acc[2 * row + 1] = fma(bi, xr, acc[2 * row + 1]);
+            }
+        }
+    }
+}
+
+template <typename T, int NB, int R, int NCH, int D, int C>
+__device__ __forceinline__ void sd_step(const typename Vec16<T>::type* __restrict__ src, int L,
+                                        typename Vec16<T>::type (&buf)[D], const T (&xv)[4][4 * NB],
+                                        const T (&xa)[4 * NB], T (&acc)[4 * R]) {
+    const typename Vec16<T>::type v = buf[C % D];
+    if constexpr (C + D < NCH) buf[C % D] = __builtin_nontemporal_load(src + (C + D) * L);
+    consume_sd<T, NB, R, C>(v, xv, xa, acc);
+}
+
+template <typename T, int NB, int R, int NCH, int D, int... Cs>
+__device__ __forceinline__ void sd_all(std::integer_sequence<int, Cs...>, const typename Vec16<T>::type* __restrict__ src,
+                                       int L, typename Vec16<T>::type (&buf)[D], const T (&xv)[4][4 * NB],
+                                       const T (&xa)[4 * NB], T (&acc)[4 * R]) {
+    (sd_step<T, NB, R, NCH, D, Cs>(src, L, buf, xv, xa, acc), ...);
+}
+
+template <typename T, int NB, int R, bool LZ>
+__global__ __launch_bounds__(64 * HX_WPB) void hx_sd_kernel(HxK a) {
+    constexpr int NO = 2 * NB;
+    constexpr int G = NB / R, A = 64 / G, L = A * G;
+    constexpr int K = 16 / sizeof(T);
+    constexpr int BC = (R * NB + K - 1) / K;
+    constexpr int OC = (2 * R * NO * 2 + K - 1) / K;
+    constexpr int NCH = 4 * BC + OC;
+    constexpr int ROW = NO * 2;                      // scalars per atom row block
+    constexpr int ROWB = ROW * int(sizeof(T));
+    constexpr int HALF = 2 * R;                      // scalars of one spin's owned rows
+    constexpr int HB = (HALF * int(sizeof(T))) % 16 == 0 ? 16 : ((HALF * int(sizeof(T))) % 8 == 0 ? 8 : 4);
+    static_assert(NCH <= HX_PIPE_MAX, "lane stream too long for the ring-buffered pipeline");
+    typedef typename Vec16<T>::type V;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t tile = blk * HX_WPB + wave;
+    const int64_t atom = tile * A + lane / G;
+    const int g = lane % G;
+    const bool active = tile < a.n_tiles && lane < L && atom < a.n_atoms;
+
+    const T* __restrict__ x = static_cast<const T*>(a.x);
+    T acc[4 * R];
+#pragma unroll
+    for (int k = 0; k < 4 * R; ++k) acc[k] = T(0);
+    double pa = 0.0, pw = 0.0;
+
+    if (active) {
+        const V* src = static_cast<const V*>(a.blocks) + tile * NCH * L + lane;
+        // own rows: orbitals gR..gR+R-1 of spin up, then of spin down
+        T xo[4 * R];
+        {
+            T h0[HALF], h1[HALF];
+            load_row<T, HALF, HB>(x + atom * ROW + g * HALF, h0);
+            load_row<T, HALF, HB>(x + atom * ROW + NB * 2 + g * HALF, h1);
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                xo[k] = h0[k];
+                xo[HALF + k] = h1[k];
+            }
+        }
+        T xv[4][ROW];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int32_t j = a.nbr[atom * 4 + b];
+            load_row<T, ROW, ROWB>(x + (j >= 0 ? int64_t(j) : atom) * ROW, xv[b]);
+        }
+        T xa[ROW];
+        load_row<T, ROW, ROWB>(x + atom * ROW, xa);
+        constexpr int D = NCH < HX_RING ? NCH : HX_RING;
+        V buf[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) buf[c] = __builtin_nontemporal_load(src + c * L);
+        sd_all<T, NB, R, NCH, D>(std::make_integer_sequence<int, NCH>{}, src, L, buf, xv, xa, acc);
+        if (a.pot) {
+            const T u = T(a.pot[atom]);
+#pragma unroll
+            for (int k = 0; k < 4 * R; ++k) acc[k] = fma(u, xo[k], acc[k]);
+        }
+        if constexpr (LZ) {
+            if (a.xprev) {
+                const T bt = T(*a.beta);
+                const T* xpv = static_cast<const T*>(a.xprev);
+                T h0[HALF], h1[HALF];
+                load_row<T, HALF, HB>(xpv + atom * ROW + g * HALF, h0);
+                load_row<T, HALF, HB>(xpv + atom * ROW + NB * 2 + g * HALF, h1);
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) {
+                    acc[k] = fma(-bt, h0[k], acc[k]);
+                    acc[HALF + k] = fma(-bt, h1[k], acc[HALF + k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4 * R; ++k) {
+                pa += double(xo[k]) * double(acc[k]);
+                pw += double(acc[k]) * double(acc[k]);
+            }
+        }
+        T* y = static_cast<T*>(a.y) + atom * ROW;
+        T h0[HALF], h1[HALF];
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            h0[k] = acc[k];
+            h1[k] = acc[HALF + k];
+        }
+        store_row<T, HALF, HB>(y + g * HALF, h0);
+        store_row<T, HALF, HB>(y + NB * 2 + g * HALF, h1);
+    }
+    if constexpr (LZ) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            pa += __shfl_xor(pa, off, 64);
+            pw += __shfl_xor(pw, off, 64);
+        }
+        if (lane == 0 && a.partial) {
+            const int64_t slot = int64_t(blockIdx.x) * HX_WPB + wave;
+            a.partial[2 * slot] = pa;
+            a.partial[2 * slot + 1] = pw;
+        }
+    }
+}
+
+template <typename T, int NB, int R>
+void launch_sd(const Layout& lay, const HxArgs& h, hipStream_t s) {
+    HxK k{};
+    k.blocks = h.blocks;
+    k.nbr = h.nbr;
+    k.x = h.x;
+    k.y = h.y;
+    k.pot = h.pot;
+    k.xprev = h.xprev;
+    k.beta = h.beta;
+    k.partial = h.partial;
+    k.n_atoms = h.n_atoms;
+    k.n_tiles = lay.n_tiles;
+    const int64_t nblk = (lay.n_tiles + HX_WPB - 1) / HX_WPB;
+    if (nblk == 0) return;
+    if (h.partial)
+        hipLaunchKernelGGL((hx_sd_kernel<T, NB, R, true>), dim3(nblk), dim3(64 * HX_WPB), 0, s, k);
+    else
+        hipLaunchKernelGGL((hx_sd_kernel<T, NB, R, false>), dim3(nblk), dim3(64 * HX_WPB), 0, s, k);
+}
+
+// ---------------------------------------------------------------------------
 // Tabulated bond blocks.  In an unstrained real H at Gamma every bond block
 // is fixed by (sublattice, species pair, bond slot): the two-centre
 // Slater-Koster form depends only on the species and the bond direction.  The
@@ -558,6 +747,19 @@ void hx_launch(const Layout& lay, bool f64, const HxArgs& h, hipStream_t s) {
         } else {
             if (lay.n_o == 5) launch_tab<float, 5>(lay, h, s);
             else launch_tab<float, 10>(lay, h, s);
+        }
+        TBH_HIP(hipGetLastError());
+        return;
+    }
+    if (lay.sd) {
+        TBH_REQUIRE((lay.n_o == 20 && lay.R == 2) || (lay.n_o == 10 && lay.R == 1),
+                    "spin-diagonal blocks: 20 orbitals with 2 rows per lane or 10 with 1");
+        if (lay.n_o == 20) {
+            if (f64) launch_sd<double, 10, 2>(lay, h, s);
+            else launch_sd<float, 10, 2>(lay, h, s);
+        } else {
+            if (f64) launch_sd<double, 5, 1>(lay, h, s);
+            else launch_sd<float, 5, 1>(lay, h, s);
         }
         TBH_HIP(hipGetLastError());
         return;

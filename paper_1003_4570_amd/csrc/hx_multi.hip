@@ -20,9 +20,10 @@
 // atom in flight at once.  The next atom's blocks and neighbour indices are
 // loaded into registers (16-byte non-temporal loads) while the current
 // atom's products run.
-// A persistent grid walks the concatenated atom range with a grid stride,
-// workgroups mapped XCD-contiguously, so that the atoms in flight form one
-// window and one XCD's L2 holds the X rows its neighbouring atoms share.
+// A persistent grid walks the concatenated atom range: either one window of
+// consecutive atoms for the whole grid (each XCD a contiguous part of it), or
+// one contiguous share per XCD swept by that XCD's workgroups, so that one
+// XCD's L2 holds the X rows its neighbouring atoms share.
 #include "tbh_internal.h"
 #include "hx_multi.h"
 
@@ -55,16 +56,29 @@ __global__ __launch_bounds__(64) void k_hx_mv(const MvDesc* __restrict__ desc, i
     __shared__ float blk[BFP];
 
     const int lane = threadIdx.x;
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, remap);
     // the table may be a slice of a larger batch: its atom range starts at
     // desc[0].atom_begin and spans `total` atoms
     const int64_t base = desc[0].atom_begin;
-    // grid-stride walk: at any moment the wavefronts in flight hold one
-    // window of `gridDim.x` consecutive atoms (each XCD a contiguous part
-    // of it), so the X rows their neighbours share stay in L2
-    const int64_t step = gridDim.x;
-    int64_t g = base + lb;
-    const int64_t g_end = base + total;
+    int64_t g, step, g_end;
+    if (remap == 2 && gridDim.x >= 8) {
+        // each XCD (workgroups are dispatched to the 8 XCDs round-robin) owns
+        // one contiguous eighth of the atoms and its workgroups sweep it in
+        // grid-stride order: successive windows on one XCD are neighbours,
+        // so the X rows one window's halo needs are the next window's own
+        // rows and stay in that XCD's L2
+        const int xcd = int(blockIdx.x % 8);
+        const int64_t idx = blockIdx.x / 8;
+        step = (int64_t(gridDim.x) - xcd + 7) / 8;
+        g = base + total * xcd / 8 + idx;
+        g_end = base + total * (xcd + 1) / 8;
+    } else {
+        // grid-stride walk: at any moment the wavefronts in flight hold one
+        // window of `gridDim.x` consecutive atoms (each XCD a contiguous part
+        // of it with remap 1)
+        step = gridDim.x;
+        g = base + xcd_block(blockIdx.x, gridDim.x, remap);
+        g_end = base + total;
+    }
     if (g >= g_end) return;
     // instance containing g
     int inst = 0;

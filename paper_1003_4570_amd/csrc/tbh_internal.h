@@ -121,8 +121,14 @@ struct Layout {
     // blocks of the tabulated launch (at most those resident on the device;
     // hx_tab_configure)
     int64_t tab_grid = 0;
+    // spin-diagonal bonds (tbh_build_opts.spin_diagonal): a lane owns R of the
+    // n_o / 2 orbitals in both spins; its stream holds, per bond, its R rows
+    // of the real n_o/2 x n_o/2 block, then its 2R complex rows of the
+    // on-site block (spin up rows, then spin down)
+    bool sd = false;
 };
 Layout make_layout(int64_t n_atoms, int n_o, bool cplx_h, int prec, int R, bool diag);
+Layout make_layout_sd(int64_t n_atoms, int n_o, int prec, int R);
 // Pack atoms into the layout (T = float or double); slot k of the stream
 // holds caller atom perm[k] (perm null: k).
 void pack_layout(const HostModel& m, const Layout& lay, bool diag, void* dst, const int64_t* perm = nullptr);

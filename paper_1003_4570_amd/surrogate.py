@@ -309,16 +309,19 @@ def near_plane_weights(study, donor_z, near_weight, half_width=3):
 
 
 def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=None, dilations=(1, 2, 4, 1),
-          near_weight=0.0, geometry="study", time_budget=None):
+          near_weight=0.0, geometry="study", time_budget=None, warmup=0):
     """Fit the network to the electron part E = U* - U_bare of converged
     potentials (added back to the exact U_bare at inference).  The targets
     are taken relative to their training mean averaged over the lattice
-    translations (an exact symmetry of the donor ensemble), and every epoch
+    translations (an exact symmetry of the donor ensemble) and divided by
+    their RMS over the nodes where they vary between layouts, and every epoch
     shows each layout under a random lattice translation.  near_weight > 0
     weights the loss on the atoms next to the donor plane.  The last n_val
-    layouts are held out and their max-norm start error reported.  The
-    learning rate follows a cosine decay from lr to zero (over epochs, or
-    over time_budget seconds when given)."""
+    layouts are held out, their max-norm start error reported every 25
+    epochs, and the parameters with the lowest median of it are the ones
+    saved.  The learning rate rises linearly over the first warmup epochs and
+    follows a cosine decay from lr to zero (over epochs, or over time_budget
+    seconds when given)."""
     import torch
     st = Study(ctx, geometry=geometry)
     X, Ub, E, seeds = load_dataset(data, st)
@@ -327,7 +330,13 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
     ntr = len(X) - n_val
     Tbar = symmetrize(E[:ntr].mean(dim=0).cpu().numpy(), grid)
     Tbar_d = torch.from_numpy(Tbar).cuda()
-    scale = float((E[:ntr] - Tbar_d).std())
+    # target scale: the spread of the electron part where it varies between
+    # layouts (near the donor plane; far from it every layout has the same
+    # potential and the map is zero), so that the targets are O(1) there
+    dev = E[:ntr] - Tbar_d
+    vox_sd = dev.std(dim=0)
+    live = vox_sd > 1e-2 * vox_sd.max()
+    scale = float(dev[:, live].pow(2).mean().sqrt())
     T = ((E - Tbar_d) / scale).float()
     nz, ny, nx = X.shape[1:]
     net = tbh.Net(st.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dilations)
@@ -348,10 +357,13 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
         return e
 
     hist = []
+    skipped = 0
+    best = (np.inf, None, -1)    # validation median, parameters, epoch
     t0 = time.perf_counter()
     for ep in range(epochs):
         frac = ep / epochs if time_budget is None else min(1.0, (time.perf_counter() - t0) / time_budget)
-        lr_ep = 0.5 * lr * (1.0 + np.cos(np.pi * frac))
+        # linear warm-up over the first warmup epochs, then cosine decay
+        lr_ep = 0.5 * lr * (1.0 + np.cos(np.pi * frac)) * min(1.0, (ep + 1) / max(1, warmup))
         order = rng.permutation(ntr)
         tot = 0.0
         for b0 in range(0, len(order), batch):
@@ -361,19 +373,31 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
                 sx, sy = shifts[rng.integers(len(shifts))]
                 xs.append(torch.roll(Xd[i], (sy, sx), dims=(2, 3)).contiguous())
                 ts.append(torch.roll(Td[i], (sy, sx), dims=(1, 2)).contiguous())
-            tot += net.train_step(xs, ts, lr=lr_ep) * len(idx)
+            loss = net.train_step(xs, ts, lr=lr_ep)
+            if np.isfinite(loss):
+                tot += loss * len(idx)
+            else:
+                skipped += 1           # the library skipped the update
         hist.append(tot / len(order))
         done = time_budget is not None and time.perf_counter() - t0 > time_budget
         if ep % 25 == 0 or ep == epochs - 1 or done:
-            rec = dict(epoch=ep, loss=hist[-1], lr=lr_ep, seconds=round(time.perf_counter() - t0, 1))
+            rec = dict(epoch=ep, loss=hist[-1], lr=lr_ep, seconds=round(time.perf_counter() - t0, 1),
+                       skipped_steps=skipped)
             if n_val:
                 ve = val_errors()
                 rec.update(val_err_median=float(np.median(ve)), val_err_max=float(np.max(ve)))
+                if np.median(ve) < best[0]:
+                    best = (float(np.median(ve)), net.get_params(), ep)
             print(json.dumps(rec), flush=True)
         if done:
             break
     torch.cuda.synchronize()
-    np.savez(out_path, params=net.get_params(), Tbar=Tbar.astype(np.float32), scale=scale, feat_scale=feat_scale,
+    params = net.get_params()
+    if best[1] is not None:
+        # the checkpoint with the lowest validation error
+        params = best[1]
+        print(json.dumps(dict(kept_epoch=best[2], val_err_median=best[0])), flush=True)
+    np.savez(out_path, params=params, Tbar=Tbar.astype(np.float32), scale=scale, feat_scale=feat_scale,
              target="E", dilations=np.array(dilations), near_weight=near_weight, loss=np.array(hist),
              train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0, geometry=geometry,
              epochs=len(hist))
@@ -460,6 +484,7 @@ def main():
     t.add_argument("--near-weight", type=float, default=0.0,
                    help="extra loss weight on the atoms next to the donor plane")
     t.add_argument("--budget", type=float, default=None, help="stop training after this many seconds")
+    t.add_argument("--warmup", type=int, default=0, help="epochs of linear learning-rate warm-up")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="1000:1016")
@@ -474,7 +499,7 @@ def main():
     elif a.cmd == "train":
         train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.val,
               dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight,
-              geometry=a.geometry, time_budget=a.budget)
+              geometry=a.geometry, time_budget=a.budget, warmup=a.warmup)
     else:
         recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean, geometry=a.geometry, newton=a.newton)
         s = summarize(recs)

@@ -306,6 +306,75 @@ def test_tabulated_lanczos_c1(ctx):
     assert np.abs(a1 - a2).max() < 1e-10 and np.abs(b1 - b2).max() < 1e-10
 
 
+SD_CASES = [
+    ("sp3d5s_so_hardwall_strain", dict(n=2, model=W.MODEL_SP3D5S, spin=1, periodic=(0, 0, 0), passivation=30.0,
+                                       strain=True)),
+    ("sp3d5s_so_periodic_potential", dict(n=2, model=W.MODEL_SP3D5S, spin=1, potential=0.3)),
+    ("sp3s_so_ragged", dict(n=3, model=W.MODEL_SP3S, spin=1, strain=True, periodic=(1, 1, 0), passivation=30.0)),
+]
+
+
+@pytest.mark.parametrize("name,case", SD_CASES, ids=[c[0] for c in SD_CASES])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spin_diagonal_hx_parity(ctx, name, case, prec):
+    """Spin-diagonal bond storage (I_2 (x) real block per bond, full complex
+    on-site block) against the oracle's CSR H.x: FP64 <= 1e-12 and FP32 <=
+    1e-5 relative plus the per-row rounding bound; the FP64 copy of an FP32
+    ham <= 1e-12; bitwise the same as the stored format in FP64 is not
+    required (the sums run in another order), the bytes are."""
+    import torch
+    kw = dict(case)
+    n = kw.pop("n")
+    p = W.problem_periodic_cube(n, seed=13, prec=prec, **kw)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, spin_diagonal=True, keep_f64=(prec == "f32")))
+    assert h.info["spin_diagonal"] == 1
+    stored = tbh.build_hamiltonian(ctx, **tbh.problem_args(p))
+    print(f"{name} {prec}: hx bytes spin-diagonal {h.info['hx_bytes']} stored {stored.info['hx_bytes']}",
+          flush=True)
+    assert h.info["hx_bytes"] < 0.5 * stored.info["hx_bytes"]
+    rng = np.random.default_rng(2)
+    x, xt = _rand_x(p, rng, True, h.torch_dtype())
+    xd = xt.cuda()
+    y = tbh.apply_h(h, xd)
+    y2 = tbh.apply_h(h, xd)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2)
+    H = T.hamiltonian(p)
+    xr = xt.numpy().astype(np.complex128)
+    yr = H @ xr
+    yg = y.cpu().numpy().astype(np.complex128)
+    row_bound_check(H, xr, yg, yr, prec)
+    err = np.linalg.norm(yg - yr) / np.linalg.norm(yr)
+    assert err <= (1e-12 if prec == "f64" else 1e-5), err
+    if prec == "f32":
+        x64 = torch.tensor(x, dtype=torch.complex128).cuda()
+        y64 = tbh.apply_h_f64(h, x64).cpu().numpy()
+        assert np.linalg.norm(y64 - H @ x) / np.linalg.norm(H @ x) <= 1e-12
+
+
+def test_spin_diagonal_lanczos_equals_stored(ctx):
+    """The fused Lanczos step through the spin-diagonal format on the C2
+    recipe at 2^3 cells (FP64): 40 coefficients equal the stored format's to
+    1e-10, and the converged values nearest mid-gap are dense eigenvalues."""
+    p = W.c2_hardwall_so(0, n=2, m=400)
+    h = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64", spin_diagonal=True))
+    hs = tbh.build_hamiltonian(ctx, **tbh.problem_args(p, prec="f64"))
+    a1, b1, _ = tbh.lanczos_run(h, 40, p.v0, reorth=False)
+    a2, b2, _ = tbh.lanczos_run(hs, 40, p.v0, reorth=False)
+    assert np.abs(a1 - a2).max() < 1e-10 and np.abs(b1 - b2).max() < 1e-10
+    r = tbh.lanczos_eigs(h, p.sigma, 4, 400, p.v0, reorth=True)
+    ev = np.linalg.eigvalsh(T.hamiltonian(p).toarray())
+    for e in r["refined"]:
+        assert np.abs(ev - e).min() < 1e-9
+
+
+@pytest.mark.parametrize("bad", [dict(spin=0), dict(spin=1, kfrac=(0.1, 0.0, 0.0))], ids=["no_spin", "kpoint"])
+def test_spin_diagonal_rejects_other_models(ctx, bad):
+    p = W.problem_periodic_cube(2, seed=3, model=W.MODEL_SP3S, **bad)
+    with pytest.raises(tbh.TBHError):
+        tbh.build_hamiltonian(ctx, **tbh.problem_args(p, spin_diagonal=True))
+
+
 def test_handles_destroyed_in_any_order():
     """Contexts, hams, SCF loops and batches may be destroyed in any order
     (a child keeps its parent alive until it is destroyed itself): here the

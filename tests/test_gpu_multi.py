@@ -108,6 +108,17 @@ def test_batched_graph_equals_separate_and_oracle(ctx, tmp_path):
     torch.cuda.synchronize()
     for a, y in zip(got, Ys):
         assert np.array_equal(a, y.cpu().numpy())
+    # every walk of the atoms (one grid-wide window, XCD-contiguous window,
+    # one contiguous share per XCD) and grid size computes the same rows
+    for remap in (0, 1, 2):
+        for grid in (1, 7, 8, 64, 1000):
+            b.configure(grid, remap)
+            for y in Ys:
+                y.fill_(-7.0)
+            b.apply()
+            torch.cuda.synchronize()
+            for a, y in zip(got, Ys):
+                assert np.array_equal(a, y.cpu().numpy()), (remap, grid)
     # replay the graph several times with eager work in between
     for r in range(3):
         for y in Ys:
