@@ -457,7 +457,8 @@ int tbh_poisson_solve_noalloc(tbh_ctx* ctx, const int32_t grid[3], double h_nm, 
  *  1. H(U) = H_TB + U at every atom's orbitals;
  *  2. Lanczos (full CGS2, lanczos_iter steps) targeted 0.05 eV below the
  *     lowest filled state of the previous step (first step, or none filled:
- *     e_cbm + min U); the n_cand Ritz pairs nearest the target with residual
+ *     e_cbm + the 1st percentile of U over the atoms); the n_cand Ritz pairs
+ *     nearest the target with residual
  *     <= res_tol are the states, their energies the FP64 Rayleigh quotients;
  *  3. conduction-band-like states (E - <psi|U|psi> > sigma_mid) are filled
  *     with spin degeneracy 2 and Fermi-Dirac occupation at T_K; the Fermi
@@ -492,7 +493,8 @@ typedef struct {
      * `block` vectors kept across steps (real H built with multi_vector = 1):
      * the fold centre is three quarters of the way from the valence-band top
      * estimate (e_vbm + max U) to the conduction-band bottom estimate (the
-     * previous step's lowest filled state, or e_cbm + min U); each step runs
+     * previous step's lowest filled state, or e_cbm + the 1st percentile of U
+     * over the atoms); each step runs
      * filters of degree filter_degree (filter_degree_cold on the first step,
      * from a random block) until the k_states pairs nearest the centre have
      * residual <= max(res_tol, 0.1 * the previous step's SCF residual), at

@@ -564,7 +564,7 @@ void block_lanczos_run(Ham& h, BlWork& W, const BlOpts& o, float* X0) {
     TBH_HIP(hipGetDevice(&dev));
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = int(std::min<int64_t>(int64_t(n_cu) * 8, h.n));
+    const int grid = int(std::min<int64_t>(int64_t(n_cu) * 32, h.n));   // 32 wavefronts per CU hide the gathers
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (o.time_hx) {
         TBH_HIP(hipEventCreate(&e0));
@@ -751,7 +751,7 @@ void mv_apply(Ham& h, BlWork& W, int slot, const float* in, float* out, double s
     TBH_HIP(hipGetDevice(&dev));
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = int(std::min<int64_t>(int64_t(n_cu) * 8, h.n));
+    const int grid = int(std::min<int64_t>(int64_t(n_cu) * 32, h.n));   // 32 wavefronts per CU hide the gathers
     mv_launch(false, h.n_o, b, W.mvdesc.as<MvDesc>() + slot, 1, h.n, grid, 1, st);
 }
 

@@ -171,41 +171,43 @@ __global__ void k_chi_apply(int64_t n_atoms, int nchunk, const double* __restric
     }
 }
 
-// x = 0, r = rhs, z = M^-1 r, p = z; partials r.z and rhs.rhs
-__global__ void k_pcg_init(int64_t n, const double* rhs, const double* minv, double* x, double* r, double* z,
-                           double* p, double* part) {
-    double rz = 0.0, bb = 0.0;
+// x = 0, r = rhs; partial rhs.rhs
+__global__ void k_pcg_init(int64_t n, const double* rhs, double* x, double* r, double* part) {
+    double bb = 0.0;
     NGRID_LOOP(i, n) {
         const double v = rhs[i];
-        const double zi = minv[i] * v;
         x[i] = 0.0;
         r[i] = v;
-        z[i] = zi;
-        p[i] = zi;
-        rz += v * zi;
         bb += v * v;
     }
-    const double t1 = block_sum(rz);
-    const double t2 = block_sum(bb);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = t1;
-        part[2 * blockIdx.x + 1] = t2;
-    }
+    const double t = block_sum(bb);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void k_pcg_init_scalars(const double* part, int64_t nb, double* s, double rel_tol) {
-    double rz = 0.0, bb = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += TPB) {
-        rz += part[2 * b];
-        bb += part[2 * b + 1];
+// z = M^-1 r with the Jacobi preconditioner
+__global__ void k_jacobi(int64_t n, const double* minv, const double* r, double* z, const double* done) {
+    if (done && *done != 0.0) return;
+    NGRID_LOOP(i, n) z[i] = minv[i] * r[i];
+}
+
+// p = z; partial r.z
+__global__ void k_pcg_first_p(int64_t n, const double* r, const double* z, double* p, double* part) {
+    double rz = 0.0;
+    NGRID_LOOP(i, n) {
+        p[i] = z[i];
+        rz += r[i] * z[i];
     }
-    rz = block_sum(rz);
-    bb = block_sum(bb);
+    const double t = block_sum(rz);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_pcg_init_scalars(const double* part_bb, const double* part_rz, int64_t nb, double* s) {
+    const double bb = sum_part(part_bb, nb);
+    const double rz = sum_part(part_rz, nb);
     if (threadIdx.x != 0) return;
     for (int k = 0; k < NC_NS; ++k) s[k] = 0.0;
     s[NC_RZ] = rz;
     s[NC_BB] = bb;
-    (void)rel_tol;
     if (bb == 0.0) s[NC_DONE] = 1.0;   // G = 0: the step is zero
 }
 
@@ -223,39 +225,28 @@ __global__ void k_pcg_alpha(const double* part, int64_t nb, double* s) {
     if (threadIdx.x == 0) s[NC_ALPHA] = pap > 0.0 ? s[NC_RZ] / pap : 0.0;
 }
 
-// x += alpha p, r -= alpha Ap, z = M^-1 r; partials r.z and r.r
-__global__ void k_pcg_update(int64_t n, double* x, double* r, double* z, const double* p, const double* Ap,
-                             const double* minv, const double* s, double* part) {
+// x += alpha p, r -= alpha Ap; partial r.r
+__global__ void k_pcg_update(int64_t n, double* x, double* r, const double* p, const double* Ap, const double* s,
+                             double* part) {
     if (s[NC_DONE] != 0.0) return;
     const double al = s[NC_ALPHA];
-    double rz = 0.0, rr = 0.0;
+    double rr = 0.0;
     NGRID_LOOP(i, n) {
         x[i] += al * p[i];
         const double rv = r[i] - al * Ap[i];
-        const double zv = minv[i] * rv;
         r[i] = rv;
-        z[i] = zv;
-        rz += rv * zv;
         rr += rv * rv;
     }
-    const double t1 = block_sum(rz);
-    const double t2 = block_sum(rr);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = t1;
-        part[2 * blockIdx.x + 1] = t2;
-    }
+    const double t = block_sum(rr);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// beta and the stopping test |r| <= rel_tol |rhs|
-__global__ void k_pcg_beta(const double* part, int64_t nb, double* s, double rel_tol, int max_iter) {
+// beta = r.z / previous r.z and the stopping test |r| <= rel_tol |rhs|
+__global__ void k_pcg_beta(const double* part_rr, const double* part_rz, int64_t nb, double* s, double rel_tol,
+                           int max_iter) {
     if (s[NC_DONE] != 0.0) return;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t b = threadIdx.x; b < nb; b += TPB) {
-        rz += part[2 * b];
-        rr += part[2 * b + 1];
-    }
-    rz = block_sum(rz);
-    rr = block_sum(rr);
+    const double rr = sum_part(part_rr, nb);
+    const double rz = sum_part(part_rz, nb);
     if (threadIdx.x != 0) return;
     s[NC_BETA] = s[NC_RZ] != 0.0 ? rz / s[NC_RZ] : 0.0;
     s[NC_RZ] = rz;
@@ -476,11 +467,23 @@ void newton_update(hipStream_t st, NewtonWork& W, const NewtonIn& in, double* U,
                        (const double*)nullptr);
     double* part = W.part.as<double>();
     double* s = W.s.as<double>();
-    hipLaunchKernelGGL(k_pcg_init, dim3(gn), dim3(TPB), 0, st, n, W.G.as<double>(), W.minv.as<double>(),
-                       W.x.as<double>(), W.r.as<double>(), W.z.as<double>(), W.p.as<double>(), part);
-    hipLaunchKernelGGL(k_pcg_init_scalars, dim3(1), dim3(TPB), 0, st, part, gn, s, in.cg_tol);
+    double* part2 = part + 4096;   // second set of partial sums (r.z)
+    auto precondition = [&](const double* done) {
+        if (in.pre)
+            in.pre->solve(st, W.r.as<double>(), W.z.as<double>());
+        else
+            hipLaunchKernelGGL(k_jacobi, dim3(gn), dim3(TPB), 0, st, n, W.minv.as<double>(), W.r.as<double>(),
+                               W.z.as<double>(), done);
+    };
+    hipLaunchKernelGGL(k_pcg_init, dim3(gn), dim3(TPB), 0, st, n, W.G.as<double>(), W.x.as<double>(),
+                       W.r.as<double>(), part);
+    precondition(nullptr);
+    hipLaunchKernelGGL(k_pcg_first_p, dim3(gn), dim3(TPB), 0, st, n, W.r.as<double>(), W.z.as<double>(),
+                       W.p.as<double>(), part2);
+    hipLaunchKernelGGL(k_pcg_init_scalars, dim3(1), dim3(TPB), 0, st, part, part2, gn, s);
     double hs[NC_NS] = {};
-    const int chunk = 20;
+    // the direct preconditioner leaves few iterations: check after each few
+    const int chunk = in.pre ? 4 : 20;
     for (int it = 0; it < in.cg_max_iter; it += chunk) {
         for (int c = 0; c < chunk; ++c) {
             hipLaunchKernelGGL(k_apply_a, dim3(gn), dim3(TPB), 0, st, nx, ny, nz, inv_h2, W.p.as<double>(),
@@ -502,8 +505,11 @@ void newton_update(hipStream_t st, NewtonWork& W, const NewtonIn& in, double* U,
                                s + NC_DONE);
             hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(TPB), 0, st, part, gn, s);
             hipLaunchKernelGGL(k_pcg_update, dim3(gn), dim3(TPB), 0, st, n, W.x.as<double>(), W.r.as<double>(),
-                               W.z.as<double>(), W.p.as<double>(), W.Ap.as<double>(), W.minv.as<double>(), s, part);
-            hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(TPB), 0, st, part, gn, s, in.cg_tol, in.cg_max_iter);
+                               W.p.as<double>(), W.Ap.as<double>(), s, part);
+            precondition(s + NC_DONE);
+            hipLaunchKernelGGL(k_pdot, dim3(gn), dim3(TPB), 0, st, n, W.r.as<double>(), W.z.as<double>(), part2,
+                               s + NC_DONE);
+            hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(TPB), 0, st, part, part2, gn, s, in.cg_tol, in.cg_max_iter);
             hipLaunchKernelGGL(k_pcg_p, dim3(gn), dim3(TPB), 0, st, n, W.z.as<double>(), W.p.as<double>(), s);
         }
         TBH_HIP(hipMemcpyAsync(hs, s, sizeof(hs), hipMemcpyDeviceToHost, st));

@@ -29,6 +29,16 @@ void poisson_cg(hipStream_t st, PoissonWork& W, const int grid[3], double h, con
 void poisson_cg_bufs(hipStream_t st, const PoissonBufs& W, const int grid[3], double h, const double* b,
                      double* x, double rel_tol, int max_iter, int* iters, double* rel_res);
 
+// Direct solve of A x = b on the loop's grid (fast_poisson.hip): Fourier
+// modes along x and y, one tridiagonal solve along z per mode
+struct FastPoisson {
+    int nx = 0, ny = 0, nz = 0;
+    double h = 0.0;
+    DevBuf W, V, cp, tw;
+    void setup(const int grid[3], double h_nm);
+    void solve(hipStream_t st, const double* b, double* x);   // x may alias b
+};
+
 // Newton-Raphson update of the loop's potential (newton.hip)
 struct NewtonWork {
     DevBuf R, coef, pairs, sel, inv, fp, diag, d, va, tpart, a, minv, x, r, z, p, Ap, G, Xp, Fp, part, s, small, dX, dF;
@@ -53,6 +63,7 @@ struct NewtonIn {
     double cg_tol;
     int cg_max_iter;
     int depth;                  // Anderson depth (0 = plain Newton steps)
+    FastPoisson* pre;           // preconditioner A^-1 of the Jacobian's CG (null: Jacobi)
 };
 struct NewtonOut {
     int cg_iters = 0;
@@ -72,6 +83,7 @@ struct Scf {
     double prev_emin = 0.0;     // lowest filled state energy of the previous step
     DevBuf node_d, b0_d, U, phi, b, Ua, v0, part, occ, q, out, n_atoms_d;
     PoissonWork pw;
+    FastPoisson fp;             // the loop's Poisson solve (checked, CG takes over if it misses)
     std::shared_ptr<LzWork> lz;
     RitzOut ritz;
     // start potential (tbh_scf_set_start) and the fallback to the zero start

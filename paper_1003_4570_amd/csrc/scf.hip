@@ -667,7 +667,21 @@ void Scf::step(tbh_scf_report& rep) {
     double mm[2];
     TBH_HIP(hipMemcpyAsync(mm, out.as<double>() + 4, 16, hipMemcpyDeviceToHost, st));
     TBH_HIP(hipStreamSynchronize(st));
-    const double u_max = mm[0], u_min = mm[1];
+    const double u_max = mm[0];
+    // without a previous step's states, the conduction-band edge is estimated
+    // as the bulk edge shifted by a low quantile of the potential over the
+    // atoms (the 1st percentile): the single-node wells a start potential
+    // carries at donor sites are too narrow to bind a state that deep, and the
+    // plain minimum would put the eigen-solve's window far below the states
+    double u_low = mm[1];
+    if (!have_prev) {
+        std::vector<double> ua(static_cast<size_t>(h->n));
+        TBH_HIP(hipMemcpyAsync(ua.data(), Ua.p, ua.size() * 8, hipMemcpyDeviceToHost, st));
+        TBH_HIP(hipStreamSynchronize(st));
+        const size_t q = size_t(0.01 * double(ua.size()));
+        std::nth_element(ua.begin(), ua.begin() + q, ua.end());
+        u_low = ua[q];
+    }
     int steps = 0, ncand = 0;
     const double* Ys = nullptr;
     const double* res4 = nullptr;
@@ -676,7 +690,7 @@ void Scf::step(tbh_scf_report& rep) {
     if (opt.eig_mode == 0) {
         // target: just below the lowest filled state of the previous step; on
         // the first step (or if none was filled) the bulk CBM shifted by min U
-        sigma = have_prev ? prev_emin - 0.05 : opt.e_cbm + u_min;
+        sigma = have_prev ? prev_emin - 0.05 : opt.e_cbm + u_low;
         if (!lz) lz = std::make_shared<LzWork>();
         int brk = 0;
         lanczos_recurrence(*h, *lz, opt.lanczos_iter, true, v0.as<double>(), nullptr, nullptr, &steps, &brk,
@@ -711,7 +725,7 @@ void Scf::step(tbh_scf_report& rep) {
             emax_b += 2.0;
             have_bounds = true;
         }
-        const double e_cb = have_prev ? prev_emin : opt.e_cbm + u_min;
+        const double e_cb = have_prev ? prev_emin : opt.e_cbm + u_low;
         const double e_vb = opt.e_vbm + u_max;
         FsSolve so;
         so.s = e_vb + 0.75 * (e_cb - e_vb);
@@ -751,9 +765,12 @@ void Scf::step(tbh_scf_report& rep) {
     hipLaunchKernelGGL(k_density_rhs, dim3(ga), dim3(TPB), 0, st, Ys, int64_t(ns), ncand,
                        h->n_o, cs, h->n, occ.as<double>(), node_d.as<int64_t>(), scale, b.as<double>(),
                        n_atoms_d.as<double>());
-    // Poisson (phi holds the previous solution as the guess)
+    // Poisson: the direct solve, then conjugate gradients from it, which stop
+    // at once when its residual already meets the tolerance
     int cg_it = 0;
     double cg_rel = 0.0;
+    fp.setup(grid, opt.h_nm);
+    fp.solve(st, b.as<double>(), phi.as<double>());
     poisson_cg(st, pw, grid, opt.h_nm, b.as<double>(), phi.as<double>(), opt.cg_tol, opt.cg_max_iter, &cg_it,
                &cg_rel);
     const auto t2 = std::chrono::steady_clock::now();
@@ -808,6 +825,7 @@ void Scf::step(tbh_scf_report& rep) {
         ni.cg_tol = opt.newton_cg_tol;
         ni.cg_max_iter = opt.newton_cg_max_iter;
         ni.depth = opt.anderson_depth;
+        ni.pre = &fp;
         NewtonOut no;
         newton_update(st, nw, ni, U.as<double>(), &no);
         rep.newton_cg_iters = no.cg_iters;

@@ -309,7 +309,7 @@ def near_plane_weights(study, donor_z, near_weight, half_width=3):
 
 
 def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=None, dilations=(1, 2, 4, 1),
-          near_weight=0.0, geometry="study", time_budget=None, warmup=0):
+          near_weight=0.0, geometry="study", time_budget=None, warmup=0, init=None):
     """Fit the network to the electron part E = U* - U_bare of converged
     potentials (added back to the exact U_bare at inference).  The targets
     are taken relative to their training mean averaged over the lattice
@@ -321,7 +321,8 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
     epochs, and the parameters with the lowest median of it are the ones
     saved.  The learning rate rises linearly over the first warmup epochs and
     follows a cosine decay from lr to zero (over epochs, or over time_budget
-    seconds when given)."""
+    seconds when given).  init: a saved network whose parameters, mean and
+    scales the training continues from (same geometry and layers)."""
     import torch
     st = Study(ctx, geometry=geometry)
     X, Ub, E, seeds = load_dataset(data, st)
@@ -329,6 +330,10 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
     feat_scale = float(Ub.std())
     ntr = len(X) - n_val
     Tbar = symmetrize(E[:ntr].mean(dim=0).cpu().numpy(), grid)
+    if init is not None:
+        w0 = np.load(init)
+        feat_scale = float(w0["feat_scale"])
+        Tbar = w0["Tbar"].astype(np.float64)
     Tbar_d = torch.from_numpy(Tbar).cuda()
     # target scale: the spread of the electron part where it varies between
     # layouts (near the donor plane; far from it every layout has the same
@@ -336,11 +341,12 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
     dev = E[:ntr] - Tbar_d
     vox_sd = dev.std(dim=0)
     live = vox_sd > 1e-2 * vox_sd.max()
-    scale = float(dev[:, live].pow(2).mean().sqrt())
+    scale = float(dev[:, live].pow(2).mean().sqrt()) if init is None else float(np.load(init)["scale"])
     T = ((E - Tbar_d) / scale).float()
     nz, ny, nx = X.shape[1:]
     net = tbh.Net(st.ctx, (nx, ny, nz), in_channels=N_IN, dilations=dilations)
-    net.set_params(W.init_surrogate_weights(seed, in_channels=N_IN, n_layers=len(dilations)))
+    net.set_params(W.init_surrogate_weights(seed, in_channels=N_IN, n_layers=len(dilations)) if init is None
+                   else np.load(init)["params"])
     if near_weight > 0:
         donor_z = int(np.flatnonzero(X.sum(axis=(0, 2, 3)))[0])
         net.set_loss_weights(torch.from_numpy(near_plane_weights(st, donor_z, near_weight)).cuda())
@@ -397,10 +403,14 @@ def train(data, out_path, epochs=300, lr=1e-3, batch=8, seed=0, n_val=0, ctx=Non
         # the checkpoint with the lowest validation error
         params = best[1]
         print(json.dumps(dict(kept_epoch=best[2], val_err_median=best[0])), flush=True)
+    prior_s, prior_ep = 0.0, 0
+    if init is not None:
+        w0 = np.load(init)
+        prior_s, prior_ep = float(w0["train_seconds"]), int(w0["epochs"])
     np.savez(out_path, params=params, Tbar=Tbar.astype(np.float32), scale=scale, feat_scale=feat_scale,
              target="E", dilations=np.array(dilations), near_weight=near_weight, loss=np.array(hist),
-             train_seeds=np.array(seeds[:ntr]), train_seconds=time.perf_counter() - t0, geometry=geometry,
-             epochs=len(hist))
+             train_seeds=np.array(seeds[:ntr]), train_seconds=prior_s + time.perf_counter() - t0, geometry=geometry,
+             epochs=prior_ep + len(hist))
     return hist
 
 
@@ -485,6 +495,7 @@ def main():
                    help="extra loss weight on the atoms next to the donor plane")
     t.add_argument("--budget", type=float, default=None, help="stop training after this many seconds")
     t.add_argument("--warmup", type=int, default=0, help="epochs of linear learning-rate warm-up")
+    t.add_argument("--init", default=None, help="continue from these saved weights")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--seeds", default="1000:1016")
@@ -499,7 +510,7 @@ def main():
     elif a.cmd == "train":
         train(a.data, a.out, a.epochs, a.lr, a.batch, a.seed, a.val,
               dilations=tuple(int(v) for v in a.dilations.split(",")), near_weight=a.near_weight,
-              geometry=a.geometry, time_budget=a.budget, warmup=a.warmup)
+              geometry=a.geometry, time_budget=a.budget, warmup=a.warmup, init=a.init)
     else:
         recs = evaluate(a.weights, _seeds(a.seeds), with_mean=not a.no_mean, geometry=a.geometry, newton=a.newton)
         s = summarize(recs)

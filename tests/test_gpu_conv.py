@@ -64,22 +64,27 @@ def test_forward_parity(ctx, grid, cin, dil):
     assert np.array_equal(net.get_params(), tbh.flatten_params(params))
 
 
-@pytest.mark.parametrize("cin", [1, 4])
-def test_gradient_parity(ctx, cin):
+@pytest.mark.parametrize("cin,grid,dil", [(1, (12, 12, 32), (1, 2, 4, 1)), (4, (12, 12, 32), (1, 2, 4, 1)),
+                                          (4, (32, 32, 40), (1, 2, 4, 8, 2, 1))],
+                         ids=["cin1", "cin4", "cin4_multichunk_6layers"])
+def test_gradient_parity(ctx, cin, grid, dil):
+    """Gradients against the oracle (FP16-rounded weights and activations,
+    FP64 arithmetic).  The 32 x 32 x 40 grid (the 8 x 8 x 60-cell slab's
+    cross-section) has 640 chunks of 64 voxels, more than the 256
+    weight-gradient workgroups, so each workgroup accumulates several."""
     import torch
-    grid = (12, 12, 32)
-    params, x, t = _setup(grid, 2, cin)
-    net = tbh.Net(ctx, grid, in_channels=cin)
+    params, x, t = _setup(grid, 2, cin, len(dil))
+    net = tbh.Net(ctx, grid, in_channels=cin, dilations=dil)
     net.set_params(tbh.flatten_params(params))
     g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
     hp = _halfp(params)
     xr = (x.astype(np.float64) if cin > 1 else x[None].astype(np.float64)).astype(np.float16).astype(np.float64)
-    out, cache = Cv.forward(xr, hp, half_acts=True)
+    out, cache = Cv.forward(xr, hp, half_acts=True, dilations=dil)
     lo, dout = Cv.mse(out, t[None].astype(np.float64))
     gr = Cv.backward(hp, cache, dout)
     assert loss == pytest.approx(lo, rel=1e-3)
-    G = tbh.unflatten_params(g, in_channels=cin)
-    for li in range(4):
+    G = tbh.unflatten_params(g, in_channels=cin, n_layers=len(dil))
+    for li in range(len(dil)):
         for k in range(2):
             ref = gr[li][k]
             err = np.linalg.norm(G[li][k] - ref) / max(np.linalg.norm(ref), 1e-30)
