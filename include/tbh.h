@@ -497,9 +497,10 @@ typedef struct {
      * over the atoms); each step runs
      * filters of degree filter_degree (filter_degree_cold on the first step,
      * from a random block) until the k_states pairs nearest the centre have
-     * residual <= max(res_tol, 0.1 * the previous step's SCF residual), at
-     * least one and at most filter_max_iter per step; every state of the block
-     * takes part in the filling. */
+     * residual <= max(res_tol, 0.1 * the previous step's SCF residual) (0.01 *
+     * with update_mode 1; max(res_tol, 0.01 eV) on the first step), at least
+     * one and at most filter_max_iter per step; every state of the block takes
+     * part in the filling. */
     int32_t eig_mode;
     int32_t block;            /* 16, 32 or 64 */
     int32_t filter_degree;

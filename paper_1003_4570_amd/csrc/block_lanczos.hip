@@ -209,19 +209,30 @@ __global__ void k_chol_defl(int b, const double* __restrict__ G, double defl_tol
         }
         __syncthreads();
     }
-    // inverse of the upper-triangular factor on the kept columns, one column per thread
-    for (int j = t; j < b; j += blockDim.x) {
-        for (int i = 0; i < b; ++i) Rinv[i * b + j] = 0.0;
-        if (sdef[j]) continue;
-        Rinv[j * b + j] = 1.0 / sR[j * b + j];
-        for (int i = j - 1; i >= 0; --i) {
-            if (sdef[i]) continue;
-            double s = 0.0;
-            for (int k = i + 1; k <= j; ++k) s += sR[i * b + k] * Rinv[k * b + j];
-            Rinv[i * b + j] = -s / sR[i * b + i];
-        }
-    }
+    // the factor goes out first; its inverse on the kept columns is then built
+    // in the same LDS array by back substitution, row by row from the bottom
+    // (every column of a row at once), reading the factor back from R
     for (int i = t; i < b * b; i += blockDim.x) R[i] = sR[i];
+    __syncthreads();
+    for (int i = t; i < b * b; i += blockDim.x) sR[i] = 0.0;
+    __syncthreads();
+    for (int i = b - 1; i >= 0; --i) {
+        if (!sdef[i]) {
+            const double rii = R[i * b + i];
+            for (int j = i + t; j < b; j += blockDim.x) {
+                if (sdef[j]) continue;
+                if (j == i) {
+                    sR[i * b + i] = 1.0 / rii;
+                } else {
+                    double s = 0.0;
+                    for (int k = i + 1; k <= j; ++k) s += R[i * b + k] * sR[k * b + j];
+                    sR[i * b + j] = -s / rii;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < b * b; i += blockDim.x) Rinv[i] = sR[i];
     __syncthreads();
     if (t == 0) {
         int nd = 0;

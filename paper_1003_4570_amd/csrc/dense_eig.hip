@@ -113,6 +113,68 @@ __global__ __launch_bounds__(HT) void k_sytrd(int n, double* __restrict__ A, dou
     if (t == 0) d[n - 1] = A[int64_t(n - 1) * n + n - 1];
 }
 
+// The same reduction for n <= 64 with the matrix staged in LDS (the
+// Rayleigh-Ritz matrices of the filtered solver): the arithmetic and its order
+// are those of k_sytrd, only the memory differs.
+constexpr int SMALLN = 64;
+constexpr int ST = 256;
+
+__global__ __launch_bounds__(ST) void k_sytrd_lds(int n, double* __restrict__ A, double* __restrict__ d,
+                                                  double* __restrict__ e, double* __restrict__ tau,
+                                                  double* __restrict__ V) {
+    __shared__ double As[SMALLN][SMALLN + 1];
+    __shared__ double v[SMALLN], w[SMALLN], sh[17];
+    const int t = threadIdx.x;
+    for (int idx = t; idx < n * n; idx += ST) As[idx / n][idx % n] = A[idx];
+    __syncthreads();
+    for (int k = 0; k + 1 < n; ++k) {
+        const int m = n - k - 1;
+        const double* xrow = &As[k][k + 1];
+        double ss = 0.0;
+        for (int i = 1 + t; i < m; i += ST) ss += xrow[i] * xrow[i];
+        ss = wg_sum(ss, sh);
+        const double alpha = xrow[0];
+        double tk = 0.0, beta = alpha, scal = 0.0;
+        if (ss > 0.0) {
+            const double nrm = sqrt(alpha * alpha + ss);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tk = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        for (int i = t; i < m; i += ST) {
+            const double vi = i == 0 ? 1.0 : (ss > 0.0 ? xrow[i] * scal : 0.0);
+            v[i] = vi;
+            V[int64_t(k) * n + i] = vi;
+        }
+        if (t == 0) {
+            d[k] = As[k][k];
+            e[k] = beta;
+            tau[k] = tk;
+        }
+        __syncthreads();
+        if (tk != 0.0) {
+            double pv = 0.0;
+            for (int i = t; i < m; i += ST) {
+                double acc = 0.0;
+                for (int j = 0; j < m; ++j) acc += As[k + 1 + j][k + 1 + i] * v[j];
+                w[i] = tk * acc;
+                pv += w[i] * v[i];
+            }
+            pv = wg_sum(pv, sh);
+            const double K = 0.5 * tk * pv;
+            for (int i = t; i < m; i += ST) w[i] -= K * v[i];
+            __syncthreads();
+            for (int i = t; i < m; i += ST) {
+                const double vi = v[i], wi = w[i];
+                for (int j = 0; j < m; ++j) As[k + 1 + j][k + 1 + i] -= v[j] * wi + w[j] * vi;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) d[n - 1] = As[n - 1][n - 1];
+    for (int idx = t; idx < n * n; idx += ST) A[idx] = As[idx / n][idx % n];
+}
+
 // number of eigenvalues of the tridiagonal (d, e) below x
 __device__ int sturm(int n, const double* d, const double* e, double x, double pivmin) {
     int cnt = 0;
@@ -142,8 +204,15 @@ __device__ void gersh(int n, const double* d, const double* e, double* lo, doubl
 
 // eigenvalues with indices lo .. lo+cnt-1 (ascending), lo = clamp(count(sigma)
 // - nc, 0, n - cnt), cnt = min(2 nc, n); window[0..cnt-1], ctl[0] = lo
-__global__ void k_bisect_window(int n, const double* d, const double* e, double sigma, int nc, double* window,
+__global__ void k_bisect_window(int n, const double* dg, const double* eg, double sigma, int nc, double* window,
                                 int* ctl) {
+    // the tridiagonal, read by every Sturm count, staged in LDS
+    __shared__ double d[MAXN], e[MAXN];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        d[i] = dg[i];
+        e[i] = i + 1 < n ? eg[i] : 0.0;
+    }
+    __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int cnt = min(2 * nc, n);
     if (t >= cnt) return;
@@ -319,7 +388,10 @@ void symm_eig_near(hipStream_t st, int n, double* A, double sigma, int nc, EigWo
     w.ensure(n, nc);
     double* d = w.d.as<double>();
     double* e = w.e.as<double>();
-    hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(HT), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
+    if (n <= SMALLN)
+        hipLaunchKernelGGL(k_sytrd_lds, dim3(1), dim3(ST), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
+    else
+        hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(HT), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
     const int cnt = std::min(2 * nc, n);
     hipLaunchKernelGGL(k_bisect_window, dim3((cnt + 63) / 64), dim3(64), 0, st, n, d, e, sigma, nc,
                        w.window.as<double>(), w.ctl.as<int>());

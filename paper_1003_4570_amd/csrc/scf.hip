@@ -218,22 +218,39 @@ __device__ double fermi(double E, double Ef, double kT) {
 
 // occupations (2 f for counted states, 0 otherwise), E_F, counts.
 // res4 = [ncand][4] (theta, residual, refined, |y|); q = <y|U|y> (unnormalised)
-__global__ void k_fermi(int ncand, const double* res4, const double* q, double res_tol, double sigma_mid,
-                        double n_elec, double kT, double ef_fixed, int use_fixed, double* occ, double* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int ncb = 0, nconv = 0;
+// One wavefront: lane t owns candidates t, t + 64, ...; sums and extrema are
+// reduced across the wavefront in a fixed order, so every lane holds the same
+// totals and takes the same bisection steps.
+__device__ __forceinline__ double wave_sum_all(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_fermi(int ncand, const double* res4, const double* q, double res_tol,
+                                              double sigma_mid, double n_elec, double kT, double ef_fixed,
+                                              int use_fixed, double* occ, double* out) {
+    const int t = threadIdx.x;
+    double ncb = 0.0, nconv = 0.0;
     double emin = INFINITY, emax = -INFINITY;
-    for (int c = 0; c < ncand; ++c) {
+    for (int c = t; c < ncand; c += 64) {
         const double r = res4[4 * c + 1], E = res4[4 * c + 2], yn = res4[4 * c + 3];
         const bool conv = r <= res_tol;
         const bool cb = conv && (E - q[c] / (yn * yn) > sigma_mid);
         nconv += conv;
         occ[c] = cb ? 1.0 : -1.0;
         if (cb) {
-            ++ncb;
+            ncb += 1.0;
             emin = fmin(emin, E);
             emax = fmax(emax, E);
         }
+    }
+    ncb = wave_sum_all(ncb);
+    nconv = wave_sum_all(nconv);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        emin = fmin(emin, __shfl_xor(emin, off, 64));
+        emax = fmax(emax, __shfl_xor(emax, off, 64));
     }
     double Ef = ef_fixed;
     if (!use_fixed && ncb > 0) {
@@ -241,28 +258,33 @@ __global__ void k_fermi(int ncand, const double* res4, const double* q, double r
         for (int it = 0; it < 400; ++it) {
             const double mid = 0.5 * (lo + hi);
             double s = 0.0;
-            for (int c = 0; c < ncand; ++c)
+            for (int c = t; c < ncand; c += 64)
                 if (occ[c] > 0) s += 2.0 * fermi(res4[4 * c + 2], mid, kT);
+            s = wave_sum_all(s);
             if (s < n_elec) lo = mid; else hi = mid;
             if (hi - lo < 1e-13) break;
         }
         Ef = 0.5 * (lo + hi);
     }
     double tot = 0.0;
-    for (int c = 0; c < ncand; ++c) {
+    for (int c = t; c < ncand; c += 64) {
         if (occ[c] > 0) {
             const double yn = res4[4 * c + 3];
-            occ[c] = 2.0 * fermi(res4[4 * c + 2], Ef, kT) / (yn * yn);
-            tot += 2.0 * fermi(res4[4 * c + 2], Ef, kT);
+            const double f2 = 2.0 * fermi(res4[4 * c + 2], Ef, kT);
+            occ[c] = f2 / (yn * yn);
+            tot += f2;
         } else {
             occ[c] = 0.0;
         }
     }
-    out[0] = Ef;
-    out[1] = ncb;
-    out[2] = nconv;
-    out[3] = tot;
-    out[6] = ncb > 0 ? emin : 0.0;
+    tot = wave_sum_all(tot);
+    if (t == 0) {
+        out[0] = Ef;
+        out[1] = ncb;
+        out[2] = nconv;
+        out[3] = tot;
+        out[6] = ncb > 0 ? emin : 0.0;
+    }
 }
 
 // electrons per atom n_i = sum_c occ_c sum_alpha |y_c(i, alpha)|^2, then
@@ -738,8 +760,11 @@ void Scf::step(tbh_scf_report& rep) {
         so.k = opt.k_states;
         // linear mixing moves U by a small fraction of the residual per step, so
         // early states need not be sharper than a tenth of it; a Newton step can
-        // move U by the whole residual, so its states are held to a hundredth
-        so.res_tol = fs_warm ? std::max(opt.res_tol, (opt.update_mode == 0 ? 0.1 : 0.01) * last_res) : opt.res_tol;
+        // move U by the whole residual, so its states are held to a hundredth.
+        // The first (cold) solve of a start stops at 0.01 eV: the next step's
+        // tolerance follows from the residual it produces
+        so.res_tol = fs_warm ? std::max(opt.res_tol, (opt.update_mode == 0 ? 0.1 : 0.01) * last_res)
+                             : std::max(opt.res_tol, 1e-2);
         sigma = so.s;
         steps = filtered_solve(*h, *blw, *fs, so, fs_warm, nullptr, nullptr);
         fs_warm = true;
