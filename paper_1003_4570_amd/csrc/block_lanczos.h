@@ -52,6 +52,7 @@ struct FsWork {
     DevBuf theta, res4;         // [b] Ritz values ascending; [b][4] (theta, residual, theta, |y|)
     DevBuf states;              // [b][dim] FP64 Ritz vectors (state-major, not normalised)
     DevBuf part;
+    std::vector<double> last_r4;   // host copy of res4 after the last solve's final Rayleigh-Ritz
     void ensure(int64_t dim, int b);
 };
 
@@ -80,6 +81,10 @@ struct FsSolve {
     int min_iter = 0, max_iter = 50;
     int k = 1;                   // pairs nearest s that must converge
     double res_tol = 1e-4;
+    // warm start only: take the filter's damping bound from the Ritz values
+    // the previous solve ended with instead of a Rayleigh-Ritz pass of the
+    // start block (for small changes of H between solves)
+    bool reuse_ritz = false;
 };
 
 // Filter iterations from the current block (warm) or a SplitMix64 block

@@ -74,34 +74,62 @@ __device__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// part[chunk][q][k][c] = sum over the chunk's rows r of Q_q[r][k] W[r][c]
+// part[chunk][q][k][c] = sum over the chunk's rows r of Q_q[r][k] W[r][c].
+// Tiles of RB rows of Q_q and W pass through LDS; while a tile's products
+// run, every thread holds its share of the next tile in registers, so the
+// loads of one tile overlap the arithmetic of the one before (a chunk is
+// swept by one workgroup, often the only one on its compute unit).  Each
+// thread accumulates a TR x TC patch in FP64, rows in ascending order.
 template <int B>
 __global__ __launch_bounds__(TPB) void k_ts_dots(int64_t rows, const float* __restrict__ Q, int64_t qstride,
                                                  int nq, const float* __restrict__ W, int64_t chunk_rows,
                                                  double* __restrict__ part) {
     constexpr int TR = B / 16, TC = B / 16, NCG = B / TC;
-    constexpr int RB = 32;
-    __shared__ float qs[RB][B], ws[RB][B];
+    constexpr int RB = 64;
+    constexpr int NV = RB * B / 4;                   // float4 per tile and operand
+    constexpr int PV = (NV + TPB - 1) / TPB;         // float4 per thread and operand
+    __shared__ __align__(16) float qs[RB][B];
+    __shared__ __align__(16) float ws[RB][B];
     const int t = threadIdx.x;
     const int tr = t / NCG, tc = t % NCG;
     const int q = blockIdx.y;
     const float* __restrict__ Qb = Q + int64_t(q) * qstride;
     const int64_t r0 = int64_t(blockIdx.x) * chunk_rows;
     const int64_t r1 = r0 + chunk_rows < rows ? r0 + chunk_rows : rows;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 pq[PV], pw[PV];
+    // element e of a tile starting at row rs: row rs + e / (B / 4), float4 e % (B / 4)
+    auto load = [&](int64_t rs) {
+        const int nr = int(r1 - rs < RB ? r1 - rs : RB);
+#pragma unroll
+        for (int p = 0; p < PV; ++p) {
+            const int e = t + p * TPB;
+            const int rr = e / (B / 4), c4 = e % (B / 4);
+            const bool ok = e < NV && rr < nr;
+            pq[p] = ok ? *reinterpret_cast<const f4*>(Qb + (rs + rr) * B + 4 * c4) : f4{0.f, 0.f, 0.f, 0.f};
+            pw[p] = ok ? *reinterpret_cast<const f4*>(W + (rs + rr) * B + 4 * c4) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
     double acc[TR][TC];
 #pragma unroll
     for (int i = 0; i < TR; ++i)
 #pragma unroll
         for (int j = 0; j < TC; ++j) acc[i][j] = 0.0;
+    if (r0 < r1) load(r0);
     for (int64_t rs = r0; rs < r1; rs += RB) {
         const int nr = int(r1 - rs < RB ? r1 - rs : RB);
-        for (int i = t; i < RB * B; i += TPB) {
-            const int rr = i / B, cc = i % B;
-            qs[rr][cc] = rr < nr ? Qb[(rs + rr) * B + cc] : 0.f;
-            ws[rr][cc] = rr < nr ? W[(rs + rr) * B + cc] : 0.f;
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < PV; ++p) {
+            const int e = t + p * TPB;
+            if (e < NV) {
+                reinterpret_cast<f4*>(&qs[0][0])[e] = pq[p];
+                reinterpret_cast<f4*>(&ws[0][0])[e] = pw[p];
+            }
         }
         __syncthreads();
-        for (int rr = 0; rr < nr; ++rr) {
+        if (rs + RB < r1) load(rs + RB);
+        auto row = [&](int rr) {
             double qv[TR], wv[TC];
 #pragma unroll
             for (int i = 0; i < TR; ++i) qv[i] = double(qs[rr][tr * TR + i]);
@@ -111,8 +139,13 @@ __global__ __launch_bounds__(TPB) void k_ts_dots(int64_t rows, const float* __re
             for (int i = 0; i < TR; ++i)
 #pragma unroll
                 for (int j = 0; j < TC; ++j) acc[i][j] = fma(qv[i], wv[j], acc[i][j]);
+        };
+        if (nr == RB) {
+#pragma unroll 8
+            for (int rr = 0; rr < RB; ++rr) row(rr);
+        } else {
+            for (int rr = 0; rr < nr; ++rr) row(rr);
         }
-        __syncthreads();
     }
     double* out = part + (int64_t(blockIdx.x) * nq + q) * B * B;
 #pragma unroll
@@ -121,49 +154,83 @@ __global__ __launch_bounds__(TPB) void k_ts_dots(int64_t rows, const float* __re
         for (int j = 0; j < TC; ++j) out[(tr * TR + i) * B + tc * TC + j] = acc[i][j];
 }
 
-// out[i] = sum over chunks of part[chunk][i], fixed order
+// out[i] = sum over chunks of part[chunk][i], in chunk order (the loads of
+// a batch of chunks are issued together, the sum stays sequential)
 __global__ void k_ts_reduce(int nchunk, int64_t ncoef, const double* __restrict__ part, double* __restrict__ out) {
     const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
     if (i >= ncoef) return;
+    constexpr int BATCH = 16;
     double s = 0.0;
-    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * ncoef + i];
+    int c = 0;
+    for (; c + BATCH <= nchunk; c += BATCH) {
+        double v[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) v[k] = part[int64_t(c + k) * ncoef + i];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) s += v[k];
+    }
+    for (; c < nchunk; ++c) s += part[int64_t(c) * ncoef + i];
     out[i] = s;
 }
 
 // MODE 0: W[r][c] -= sum_q sum_k Q_q[r][k] C[q][k][c]
 // MODE 1: W[r][c]  = sum_k Q_0[r][k] C[0][k][c]        (W and Q distinct)
+// The FP64 coefficient block of each q sits in LDS.  A thread owns RPT rows
+// x CPT columns (rows rl + i GROUPS of the workgroup's span, so a
+// wavefront's rows are adjacent), and every coefficient it reads from LDS
+// serves RPT rows.  Per element the sum runs over q, then k, ascending.
 template <int B, int MODE>
 __global__ __launch_bounds__(TPB) void k_ts_update(int64_t rows, const float* __restrict__ Q, int64_t qstride,
                                                    int nq, const double* __restrict__ C, float* __restrict__ W) {
-    constexpr int CPT = 16, TPR = B / CPT, RPW = TPB / TPR;
+    constexpr int CPT = 8, TPR = B / CPT, GROUPS = TPB / TPR, RPT = 4, RPB = GROUPS * RPT;
     __shared__ double cs[B * B];
+    typedef float f4 __attribute__((ext_vector_type(4)));
     const int t = threadIdx.x;
     const int rl = t / TPR, cg = t % TPR;
-    const int64_t r = int64_t(blockIdx.x) * RPW + rl;
-    double acc[CPT];
+    const int64_t rbase = int64_t(blockIdx.x) * RPB + rl;
+    double acc[RPT][CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) acc[j] = 0.0;
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) acc[i][j] = 0.0;
     for (int q = 0; q < nq; ++q) {
         __syncthreads();
         for (int i = t; i < B * B; i += TPB) cs[i] = C[int64_t(q) * B * B + i];
         __syncthreads();
-        if (r < rows) {
-            const float* __restrict__ qrow = Q + int64_t(q) * qstride + r * B;
-            for (int k = 0; k < B; ++k) {
-                const double qk = double(qrow[k]);
+        const float* __restrict__ Qq = Q + int64_t(q) * qstride;
+        for (int k0 = 0; k0 < B; k0 += 4) {
+            f4 qv[RPT];
 #pragma unroll
-                for (int j = 0; j < CPT; ++j) acc[j] = fma(qk, cs[k * B + cg * CPT + j], acc[j]);
+            for (int i = 0; i < RPT; ++i) {
+                const int64_t r = rbase + int64_t(i) * GROUPS;
+                qv[i] = r < rows ? *reinterpret_cast<const f4*>(Qq + r * B + k0) : f4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                double cv[CPT];
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) cv[j] = cs[(k0 + kk) * B + cg * CPT + j];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const double qk = double(qv[i][kk]);
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j) acc[i][j] = fma(qk, cv[j], acc[i][j]);
+                }
             }
         }
     }
-    if (r >= rows) return;
-    float* __restrict__ wrow = W + r * B + cg * CPT;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-        if constexpr (MODE == 0)
-            wrow[j] = float(double(wrow[j]) - acc[j]);
-        else
-            wrow[j] = float(acc[j]);
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t r = rbase + int64_t(i) * GROUPS;
+        if (r >= rows) continue;
+        float* __restrict__ wrow = W + r * B + cg * CPT;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            if constexpr (MODE == 0)
+                wrow[j] = float(double(wrow[j]) - acc[i][j]);
+            else
+                wrow[j] = float(acc[i][j]);
+        }
     }
 }
 
@@ -178,62 +245,69 @@ enum { CT_HNORM = 0, CT_NDEFL = 1, CT_NCTL = 8 };
 __global__ void k_chol_defl(int b, const double* __restrict__ G, double defl_tol, int ref_mode,
                             double* __restrict__ R, double* __restrict__ Rinv, int* __restrict__ defl,
                             double* __restrict__ ctl) {
+    // sR holds G's upper triangle, overwritten row by row by the factor; the
+    // inverse is then built column by column into the strictly lower
+    // triangle (Rinv[i][j] at sR[j][i], i < j), its diagonal in sDg
     __shared__ double sR[64 * 64];
+    __shared__ double sDg[64];
     __shared__ int sdef[64];
     const int t = threadIdx.x;
-    for (int i = t; i < b * b; i += blockDim.x) sR[i] = 0.0;
+    for (int i = t; i < b * b; i += blockDim.x) sR[i] = (i % b >= i / b) ? G[i] : 0.0;
+    __syncthreads();
     double ref = 0.0;
     if (ref_mode == 1) {
-        for (int i = 0; i < b; ++i) ref = fmax(ref, G[i * b + i]);
+        for (int i = 0; i < b; ++i) ref = fmax(ref, sR[i * b + i]);
         ref = sqrt(ref);
     } else {
         ref = ctl[CT_HNORM];
     }
     const double thr2 = (defl_tol * ref) * (defl_tol * ref);
-    __syncthreads();
+    // right-looking: once row i of the factor is known, every element (r, c)
+    // of the trailing upper triangle subtracts R[i][r] R[i][c] at once, so
+    // each element sees the subtractions in the order k = 0, 1, ... as in
+    // the row-by-row (left-looking) form
     for (int i = 0; i < b; ++i) {
-        // pivot
-        double r2 = G[i * b + i];
-        for (int k = 0; k < i; ++k) r2 -= sR[k * b + i] * sR[k * b + i];
+        const double r2 = sR[i * b + i];
         const bool dropped = !(r2 > thr2);
         const double rii = dropped ? 0.0 : sqrt(r2);
+        for (int j = i + 1 + t; j < b; j += blockDim.x) sR[i * b + j] = dropped ? 0.0 : sR[i * b + j] / rii;
+        __syncthreads();   // row i is final; every read of its pivot is done
         if (t == 0) {
             sdef[i] = dropped ? 1 : 0;
             sR[i * b + i] = rii;
         }
-        // the rest of row i
-        for (int j = i + 1 + t; j < b; j += blockDim.x) {
-            double s = G[i * b + j];
-            for (int k = 0; k < i; ++k) s -= sR[k * b + i] * sR[k * b + j];
-            sR[i * b + j] = dropped ? 0.0 : s / rii;
+        // thread c owns column c of the trailing block
+        for (int c = i + 1 + t; c < b; c += blockDim.x) {
+            const double ric = sR[i * b + c];
+#pragma unroll 8
+            for (int r = i + 1; r <= c; ++r) sR[r * b + c] -= sR[i * b + r] * ric;
         }
         __syncthreads();
     }
-    // the factor goes out first; its inverse on the kept columns is then built
-    // in the same LDS array by back substitution, row by row from the bottom
-    // (every column of a row at once), reading the factor back from R
-    for (int i = t; i < b * b; i += blockDim.x) R[i] = sR[i];
-    __syncthreads();
-    for (int i = t; i < b * b; i += blockDim.x) sR[i] = 0.0;
-    __syncthreads();
-    for (int i = b - 1; i >= 0; --i) {
-        if (!sdef[i]) {
-            const double rii = R[i * b + i];
-            for (int j = i + t; j < b; j += blockDim.x) {
-                if (sdef[j]) continue;
-                if (j == i) {
-                    sR[i * b + i] = 1.0 / rii;
-                } else {
-                    double s = 0.0;
-                    for (int k = i + 1; k <= j; ++k) s += R[i * b + k] * sR[k * b + j];
-                    sR[i * b + j] = -s / rii;
-                }
+    // the factor goes out
+    for (int i = t; i < b * b; i += blockDim.x) R[i] = (i % b >= i / b) ? sR[i] : 0.0;
+    // its inverse on the kept columns: column j by back substitution from the
+    // bottom, each column by one thread (no column reads another)
+    for (int j = t; j < b; j += blockDim.x) {
+        const bool dj = sdef[j] != 0;
+        sDg[j] = dj ? 0.0 : 1.0 / sR[j * b + j];
+        for (int i = j - 1; i >= 0; --i) {
+            double v = 0.0;
+            if (!dj && !sdef[i]) {
+                double s = 0.0;
+#pragma unroll 8
+                for (int k = i + 1; k < j; ++k) s += sR[i * b + k] * sR[j * b + k];
+                s += sR[i * b + j] * sDg[j];
+                v = -s / sR[i * b + i];
             }
+            sR[j * b + i] = v;
         }
-        __syncthreads();
     }
-    for (int i = t; i < b * b; i += blockDim.x) Rinv[i] = sR[i];
     __syncthreads();
+    for (int e = t; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e % b;
+        Rinv[e] = i < j ? sR[j * b + i] : (i == j ? sDg[i] : 0.0);
+    }
     if (t == 0) {
         int nd = 0;
         for (int i = 0; i < b; ++i) {
@@ -244,12 +318,20 @@ __global__ void k_chol_defl(int b, const double* __restrict__ G, double defl_tol
     }
 }
 
-// C = A B (b x b); transpose_a: C = A^T B.  One workgroup.
+// C = A B (b x b); transpose_a: C = A^T B.  One workgroup, both operands
+// staged in LDS (A transposed on the way in when asked); C may alias A or B.
 __global__ void k_small_mm(int b, const double* A, const double* Bm, double* C, int transpose_a) {
+    __shared__ double sA[64 * 64], sB[64 * 64];
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, k = e % b;
+        sA[e] = transpose_a ? A[k * b + i] : A[e];
+        sB[e] = Bm[e];
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
         const int i = e / b, j = e % b;
         double s = 0.0;
-        for (int k = 0; k < b; ++k) s += (transpose_a ? A[k * b + i] : A[i * b + k]) * Bm[k * b + j];
+        for (int k = 0; k < b; ++k) s += sA[i * b + k] * sB[k * b + j];
         C[e] = s;
     }
 }
@@ -436,8 +518,8 @@ void ts_dots(const TsCtx& c, const float* Q, int nq, const float* X, double* C) 
 template <int MODE>
 void ts_update(const TsCtx& c, const float* Q, int nq, const double* C, float* X) {
     const int64_t qs = c.rows * c.b;
-    const int rpw = TPB / (c.b / 16);
-    const dim3 g(unsigned((c.rows + rpw - 1) / rpw));
+    const int rpb = 4 * (TPB / (c.b / 8));   // rows per workgroup: 4 per thread, b / 8 threads per row
+    const dim3 g(unsigned((c.rows + rpb - 1) / rpb));
     switch (c.b) {
         case 16: hipLaunchKernelGGL((k_ts_update<16, MODE>), g, dim3(TPB), 0, c.st, c.rows, Q, qs, nq, C, X); break;
         case 32: hipLaunchKernelGGL((k_ts_update<32, MODE>), g, dim3(TPB), 0, c.st, c.rows, Q, qs, nq, C, X); break;
@@ -707,15 +789,29 @@ __global__ __launch_bounds__(TPB) void k_col_sq(int64_t rows, int b, const float
         part[int64_t(blockIdx.x) * b + c] = (sh[c] + sh[64 + c]) + (sh[128 + c] + sh[192 + c]);
 }
 
-// res4[c] = (theta, residual, theta, |y|) from the two column sums
-__global__ void k_fs_res(int nchunk, int b, const double* __restrict__ pr, const double* __restrict__ pn,
-                         const double* __restrict__ theta, double* __restrict__ res4) {
-    const int c = threadIdx.x;
-    if (c >= b) return;
+// res4[c] = (theta, residual, theta, |y|) from the two column sums.  64
+// columns x 16 slices: slice s adds chunks s, s + 16, ... in order, then
+// the slices are added in order.
+__global__ __launch_bounds__(1024) void k_fs_res(int nchunk, int b, const double* __restrict__ pr,
+                                                 const double* __restrict__ pn, const double* __restrict__ theta,
+                                                 double* __restrict__ res4) {
+    __shared__ double sr[16][64], sy[16][64];
+    const int c = threadIdx.x & 63, sl = threadIdx.x >> 6;
     double r = 0.0, y = 0.0;
-    for (int k = 0; k < nchunk; ++k) {
-        r += pr[int64_t(k) * b + c];
-        y += pn[int64_t(k) * b + c];
+    if (c < b)
+        for (int k = sl; k < nchunk; k += 16) {
+            r += pr[int64_t(k) * b + c];
+            y += pn[int64_t(k) * b + c];
+        }
+    sr[sl][c] = r;
+    sy[sl][c] = y;
+    __syncthreads();
+    if (sl != 0 || c >= b) return;
+    r = 0.0;
+    y = 0.0;
+    for (int k = 0; k < 16; ++k) {
+        r += sr[k][c];
+        y += sy[k][c];
     }
     const double yn = sqrt(y);
     res4[4 * c + 0] = theta[c];
@@ -848,7 +944,7 @@ void chfsi_rayleigh_ritz(Ham& h, BlWork& W, FsWork& F, bool states) {
     hipLaunchKernelGGL(k_col_sq, dim3(nch), dim3(TPB), 0, st, h.dim, b, HYr, Yr, F.theta.as<double>(), chunk, pr);
     hipLaunchKernelGGL(k_col_sq, dim3(nch), dim3(TPB), 0, st, h.dim, b, Yr, (const float*)nullptr,
                        (const double*)nullptr, chunk, pn);
-    hipLaunchKernelGGL(k_fs_res, dim3(1), dim3(64), 0, st, nch, b, pr, pn, F.theta.as<double>(), F.res4.as<double>());
+    hipLaunchKernelGGL(k_fs_res, dim3(1), dim3(1024), 0, st, nch, b, pr, pn, F.theta.as<double>(), F.res4.as<double>());
     if (states)
         hipLaunchKernelGGL(k_block_to_states, dim3(unsigned((h.dim * b + TPB - 1) / TPB)), dim3(TPB), 0, st, h.dim,
                            b, Yr, F.states.as<double>());
@@ -911,7 +1007,10 @@ int filtered_solve(Ham& h, BlWork& W, FsWork& F, const FsSolve& o, bool warm, do
             if (!(r4[4 * order[size_t(t)] + 1] <= o.res_tol)) return false;
         return true;
     };
-    rr(false);
+    if (warm && o.reuse_ritz && F.last_r4.size() == r4.size() && o.min_iter >= 1)
+        r4 = F.last_r4;
+    else
+        rr(false);
     const double fmax = std::max((o.emax - o.s) * (o.emax - o.s), (o.emin - o.s) * (o.emin - o.s));
     int it = 0;
     while (it < o.max_iter && (it < o.min_iter || !converged())) {
@@ -933,6 +1032,7 @@ int filtered_solve(Ham& h, BlWork& W, FsWork& F, const FsSolve& o, bool warm, do
     hipLaunchKernelGGL(k_block_to_states, dim3(unsigned((h.dim * b + TPB - 1) / TPB)), dim3(TPB), 0, st, h.dim, b,
                        F.Y.as<float>(), F.states.as<double>());
     TBH_HIP(hipGetLastError());
+    F.last_r4 = r4;
     if (theta_h) for (int c = 0; c < b; ++c) theta_h[c] = r4[4 * c];
     if (res4_h) std::copy(r4.begin(), r4.end(), res4_h);
     return it;

@@ -113,27 +113,28 @@ __global__ __launch_bounds__(HT) void k_sytrd(int n, double* __restrict__ A, dou
     if (t == 0) d[n - 1] = A[int64_t(n - 1) * n + n - 1];
 }
 
-// The same reduction for n <= 64 with the matrix staged in LDS (the
-// Rayleigh-Ritz matrices of the filtered solver): the arithmetic and its order
-// are those of k_sytrd, only the memory differs.
+// The same reduction for n <= 64 (the Rayleigh-Ritz matrices of the filtered
+// solver) on one wavefront with the matrix in LDS: lane c owns column c.  The
+// products and updates run over all 64 rows with v and w zero outside the
+// active block, so their loops have fixed bounds and every LDS access of a
+// step is independent of the others; the sums over rows are in ascending row
+// order as in k_sytrd, the two scalar sums are wavefront reductions.
 constexpr int SMALLN = 64;
-constexpr int ST = 256;
 
-__global__ __launch_bounds__(ST) void k_sytrd_lds(int n, double* __restrict__ A, double* __restrict__ d,
+__global__ __launch_bounds__(64) void k_sytrd_lds(int n, double* __restrict__ A, double* __restrict__ d,
                                                   double* __restrict__ e, double* __restrict__ tau,
                                                   double* __restrict__ V) {
     __shared__ double As[SMALLN][SMALLN + 1];
-    __shared__ double v[SMALLN], w[SMALLN], sh[17];
-    const int t = threadIdx.x;
-    for (int idx = t; idx < n * n; idx += ST) As[idx / n][idx % n] = A[idx];
+    __shared__ double va[SMALLN], wa[SMALLN];
+    const int c = threadIdx.x;
+    const bool cin = c < n;
+    for (int j = 0; j < SMALLN; ++j) As[j][c] = (j < n && cin) ? A[j * n + c] : 0.0;
     __syncthreads();
     for (int k = 0; k + 1 < n; ++k) {
-        const int m = n - k - 1;
-        const double* xrow = &As[k][k + 1];
-        double ss = 0.0;
-        for (int i = 1 + t; i < m; i += ST) ss += xrow[i] * xrow[i];
-        ss = wg_sum(ss, sh);
-        const double alpha = xrow[0];
+        const bool act = c > k && cin;              // column k + 1 + i of the trailing block
+        const double xc = act ? As[k][c] : 0.0;     // x_i, row k right of the diagonal
+        const double ss = wave_sum(c > k + 1 && cin ? xc * xc : 0.0);
+        const double alpha = As[k][k + 1];
         double tk = 0.0, beta = alpha, scal = 0.0;
         if (ss > 0.0) {
             const double nrm = sqrt(alpha * alpha + ss);
@@ -141,38 +142,33 @@ __global__ __launch_bounds__(ST) void k_sytrd_lds(int n, double* __restrict__ A,
             tk = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        for (int i = t; i < m; i += ST) {
-            const double vi = i == 0 ? 1.0 : (ss > 0.0 ? xrow[i] * scal : 0.0);
-            v[i] = vi;
-            V[int64_t(k) * n + i] = vi;
-        }
-        if (t == 0) {
+        const double vc = act ? (c == k + 1 ? 1.0 : (ss > 0.0 ? xc * scal : 0.0)) : 0.0;
+        if (act) V[int64_t(k) * n + (c - k - 1)] = vc;
+        if (c == 0) {
             d[k] = As[k][k];
             e[k] = beta;
             tau[k] = tk;
         }
+        va[c] = vc;
         __syncthreads();
         if (tk != 0.0) {
-            double pv = 0.0;
-            for (int i = t; i < m; i += ST) {
-                double acc = 0.0;
-                for (int j = 0; j < m; ++j) acc += As[k + 1 + j][k + 1 + i] * v[j];
-                w[i] = tk * acc;
-                pv += w[i] * v[i];
-            }
-            pv = wg_sum(pv, sh);
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < SMALLN; ++j) acc += As[j][c] * va[j];
+            double wc = act ? tk * acc : 0.0;
+            const double pv = wave_sum(wc * vc);
             const double K = 0.5 * tk * pv;
-            for (int i = t; i < m; i += ST) w[i] -= K * v[i];
+            wc -= K * vc;
+            wa[c] = wc;
             __syncthreads();
-            for (int i = t; i < m; i += ST) {
-                const double vi = v[i], wi = w[i];
-                for (int j = 0; j < m; ++j) As[k + 1 + j][k + 1 + i] -= v[j] * wi + w[j] * vi;
-            }
+#pragma unroll
+            for (int j = 0; j < SMALLN; ++j) As[j][c] -= va[j] * wc + wa[j] * vc;
         }
         __syncthreads();
     }
-    if (t == 0) d[n - 1] = As[n - 1][n - 1];
-    for (int idx = t; idx < n * n; idx += ST) A[idx] = As[idx / n][idx % n];
+    if (c == 0) d[n - 1] = As[n - 1][n - 1];
+    for (int j = 0; j < n; ++j)
+        if (cin) A[j * n + c] = As[j][c];
 }
 
 // number of eigenvalues of the tridiagonal (d, e) below x
@@ -256,21 +252,16 @@ __global__ void k_pick_window(int n, const double* window, double sigma, int nc,
     for (int c = 0; c < nc; ++c) theta[c] = window[lo + 1 + c];
 }
 
-// inverse iteration (T - theta_c I) s = b, one thread per candidate; work:
-// [nc][5 n] scratch
-__global__ void k_invit(int n, const double* d, const double* e, const double* theta, int nc, double* S,
-                        double* work) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const double th = theta[c];
+// inverse iteration (T - theta_c I) s = b for candidate c: partial-pivot LU
+// of the shifted tridiagonal, then three solves from a SplitMix64 start
+// vector of the candidate's own.  Element i of the LU arrays and of s sits at
+// index i * st of its array (st = 1: the candidate's own scratch; st > 1:
+// arrays interleaved over the candidates of a workgroup).
+__device__ void invit_one(int n, const double* d, const double* e, double th, int c, double* dd, double* u1,
+                          double* u2, double* l, double* piv, double* s, int st) {
     double lo, hi, tn;
     gersh(n, d, e, &lo, &hi, &tn);
     const double tiny = fmax(tn, 1e-300) * 2.220446049250313e-16;
-    double* dd = work + int64_t(c) * 5 * n;   // diagonal of U
-    double* u1 = dd + n;                       // first superdiagonal
-    double* u2 = u1 + n;                       // second superdiagonal (from row swaps)
-    double* l = u2 + n;                        // multipliers
-    double* piv = l + n;                       // 1 if rows i, i+1 were swapped
     double dcur = d[0] - th, ucur = n > 1 ? e[0] : 0.0;
     for (int i = 0; i < n - 1; ++i) {
         const double sub = e[i];
@@ -278,48 +269,78 @@ __global__ void k_invit(int n, const double* d, const double* e, const double* t
         const double unext = i + 2 < n ? e[i + 1] : 0.0;
         if (fabs(dcur) >= fabs(sub)) {
             const double p = fabs(dcur) < tiny ? tiny : dcur;
-            l[i] = sub / p;
-            dd[i] = p;
-            u1[i] = ucur;
-            u2[i] = 0.0;
-            piv[i] = 0.0;
-            dcur = dnext - l[i] * ucur;
+            const double li = sub / p;
+            l[i * st] = li;
+            dd[i * st] = p;
+            u1[i * st] = ucur;
+            u2[i * st] = 0.0;
+            piv[i * st] = 0.0;
+            dcur = dnext - li * ucur;
             ucur = unext;
         } else {
-            l[i] = dcur / sub;
-            dd[i] = sub;
-            u1[i] = dnext;
-            u2[i] = unext;
-            piv[i] = 1.0;
-            dcur = ucur - l[i] * dnext;
-            ucur = -l[i] * unext;
+            const double li = dcur / sub;
+            l[i * st] = li;
+            dd[i * st] = sub;
+            u1[i * st] = dnext;
+            u2[i * st] = unext;
+            piv[i * st] = 1.0;
+            dcur = ucur - li * dnext;
+            ucur = -li * unext;
         }
     }
-    dd[n - 1] = fabs(dcur) < tiny ? tiny : dcur;
-    double* s = S + int64_t(c) * n;
-    // a start vector of its own for every candidate (SplitMix64 values in [-1, 1))
+    dd[(n - 1) * st] = fabs(dcur) < tiny ? tiny : dcur;
     for (int i = 0; i < n; ++i) {
         const uint64_t r = splitmix64((uint64_t(c) << 32) + uint64_t(i));
-        s[i] = double(r >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+        s[i * st] = double(r >> 11) * 0x1.0p-53 * 2.0 - 1.0;
     }
     for (int it = 0; it < 3; ++it) {
         for (int i = 0; i < n - 1; ++i) {
-            if (piv[i] != 0.0) {
-                const double tt = s[i];
-                s[i] = s[i + 1];
-                s[i + 1] = tt - l[i] * s[i];
+            if (piv[i * st] != 0.0) {
+                const double tt = s[i * st];
+                s[i * st] = s[(i + 1) * st];
+                s[(i + 1) * st] = tt - l[i * st] * s[i * st];
             } else {
-                s[i + 1] -= l[i] * s[i];
+                s[(i + 1) * st] -= l[i * st] * s[i * st];
             }
         }
-        s[n - 1] /= dd[n - 1];
-        if (n > 1) s[n - 2] = (s[n - 2] - u1[n - 2] * s[n - 1]) / dd[n - 2];
-        for (int i = n - 3; i >= 0; --i) s[i] = (s[i] - u1[i] * s[i + 1] - u2[i] * s[i + 2]) / dd[i];
+        s[(n - 1) * st] /= dd[(n - 1) * st];
+        if (n > 1) s[(n - 2) * st] = (s[(n - 2) * st] - u1[(n - 2) * st] * s[(n - 1) * st]) / dd[(n - 2) * st];
+        for (int i = n - 3; i >= 0; --i)
+            s[i * st] = (s[i * st] - u1[i * st] * s[(i + 1) * st] - u2[i * st] * s[(i + 2) * st]) / dd[i * st];
         double nr = 0.0;
-        for (int i = 0; i < n; ++i) nr += s[i] * s[i];
+        for (int i = 0; i < n; ++i) nr += s[i * st] * s[i * st];
         nr = 1.0 / sqrt(nr);
-        for (int i = 0; i < n; ++i) s[i] *= nr;
+        for (int i = 0; i < n; ++i) s[i * st] *= nr;
     }
+}
+
+// one thread per candidate; work: [nc][5 n] scratch
+__global__ void k_invit(int n, const double* d, const double* e, const double* theta, int nc, double* S,
+                        double* work) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double* w = work + int64_t(c) * 5 * n;
+    invit_one(n, d, e, theta[c], c, w, w + n, w + 2 * n, w + 3 * n, w + 4 * n, S + int64_t(c) * n, 1);
+}
+
+// the same for n <= 64 with the tridiagonal, the LU arrays and the vectors in
+// LDS, interleaved over the IC candidates of the workgroup (one thread each)
+constexpr int IC = 16;
+
+__global__ __launch_bounds__(IC) void k_invit_lds(int n, const double* dg, const double* eg,
+                                                  const double* theta, int nc, double* S) {
+    __shared__ double sd[64], se[64];
+    __shared__ double lu[5][64][IC], sv[64][IC];
+    for (int i = threadIdx.x; i < n; i += IC) {
+        sd[i] = dg[i];
+        se[i] = i + 1 < n ? eg[i] : 0.0;
+    }
+    __syncthreads();
+    const int j = threadIdx.x, c = blockIdx.x * IC + j;
+    if (c >= nc) return;
+    invit_one(n, sd, se, theta[c], c, &lu[0][0][j], &lu[1][0][j], &lu[2][0][j], &lu[3][0][j], &lu[4][0][j],
+              &sv[0][j], IC);
+    for (int i = 0; i < n; ++i) S[int64_t(c) * n + i] = sv[i][j];
 }
 
 // Gram-Schmidt (twice) of each candidate against the earlier candidates of
@@ -389,15 +410,18 @@ void symm_eig_near(hipStream_t st, int n, double* A, double sigma, int nc, EigWo
     double* d = w.d.as<double>();
     double* e = w.e.as<double>();
     if (n <= SMALLN)
-        hipLaunchKernelGGL(k_sytrd_lds, dim3(1), dim3(ST), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
+        hipLaunchKernelGGL(k_sytrd_lds, dim3(1), dim3(64), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
     else
         hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(HT), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
     const int cnt = std::min(2 * nc, n);
     hipLaunchKernelGGL(k_bisect_window, dim3((cnt + 63) / 64), dim3(64), 0, st, n, d, e, sigma, nc,
                        w.window.as<double>(), w.ctl.as<int>());
     hipLaunchKernelGGL(k_pick_window, dim3(1), dim3(64), 0, st, n, w.window.as<double>(), sigma, nc, theta);
-    hipLaunchKernelGGL(k_invit, dim3((nc + 63) / 64), dim3(64), 0, st, n, d, e, theta, nc, S,
-                       w.work.as<double>());
+    if (n <= SMALLN)
+        hipLaunchKernelGGL(k_invit_lds, dim3((nc + IC - 1) / IC), dim3(IC), 0, st, n, d, e, theta, nc, S);
+    else
+        hipLaunchKernelGGL(k_invit, dim3((nc + 63) / 64), dim3(64), 0, st, n, d, e, theta, nc, S,
+                           w.work.as<double>());
     hipLaunchKernelGGL(k_cluster_orth, dim3(1), dim3(256), 0, st, n, d, e, theta, nc, S);
     hipLaunchKernelGGL(k_back_transform, dim3(nc), dim3(256), 0, st, n, w.V.as<double>(), w.tau.as<double>(), S);
     TBH_HIP(hipGetLastError());

@@ -99,6 +99,7 @@ struct Scf {
     std::shared_ptr<BlWork> blw;
     std::shared_ptr<FsWork> fs;
     bool fs_warm = false, have_bounds = false;
+    bool fs_reuse = false;      // the block's last Ritz values describe the current start
     DevBuf U_bounds;            // the potential the spectral bounds were taken at
     double emin_b = 0.0, emax_b = 0.0, last_res = 0.0;
     // Newton-Raphson update (update_mode 1)

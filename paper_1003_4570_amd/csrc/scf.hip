@@ -666,6 +666,7 @@ void Scf::set_potential(const double* Ud) {
     have_prev = false;
     nw.reset();
     have_bounds = false;
+    fs_reuse = false;
     last_res = 0.0;
     start_kind = 0;
     since_start = 0;
@@ -765,9 +766,15 @@ void Scf::step(tbh_scf_report& rep) {
         // tolerance follows from the residual it produces
         so.res_tol = fs_warm ? std::max(opt.res_tol, (opt.update_mode == 0 ? 0.1 : 0.01) * last_res)
                              : std::max(opt.res_tol, 1e-2);
+        // a linear-mixing step moves U by a small fraction of the residual, so
+        // the Ritz values the last solve ended with still bound the block's
+        // spectrum for the filter: the Rayleigh-Ritz pass of the start block
+        // is skipped
+        so.reuse_ritz = fs_warm && fs_reuse && opt.update_mode == 0;
         sigma = so.s;
         steps = filtered_solve(*h, *blw, *fs, so, fs_warm, nullptr, nullptr);
         fs_warm = true;
+        fs_reuse = true;
         ncand = opt.block;
         Ys = fs->states.as<double>();
         res4 = fs->res4.as<double>();
