@@ -24,6 +24,12 @@ struct BlWork {
     EigWork eig;
     int deflated = 0;     // deflated columns over the last run
     double hx_ms = 0.0;   // H.X time of the last run (when timed)
+    // launch shape of the filter's multi-vector products (persistent grid and
+    // atom walk), picked by timing the candidates on the first product for
+    // a given (H, b); the products do not depend on it
+    const void* mv_key = nullptr;
+    int64_t mv_n = 0;
+    int mv_b = 0, mv_grid = 0, mv_remap = 1;
     void ensure(const Ham& h, int b, int m, int nc);
 };
 

@@ -154,23 +154,34 @@ __global__ __launch_bounds__(TPB) void k_ts_dots(int64_t rows, const float* __re
         for (int j = 0; j < TC; ++j) out[(tr * TR + i) * B + tc * TC + j] = acc[i][j];
 }
 
-// out[i] = sum over chunks of part[chunk][i], in chunk order (the loads of
-// a batch of chunks are issued together, the sum stays sequential)
-__global__ void k_ts_reduce(int nchunk, int64_t ncoef, const double* __restrict__ part, double* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x;
-    if (i >= ncoef) return;
-    constexpr int BATCH = 16;
+// out[i] = sum over chunks of part[chunk][i]: 16 coefficients x 16 slices per
+// workgroup, slice s adding chunks s, s + 16, ... in order (loads issued in
+// batches), then the slices added in order
+__global__ __launch_bounds__(TPB) void k_ts_reduce(int nchunk, int64_t ncoef, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[16][17];
+    const int c = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    const int64_t i = int64_t(blockIdx.x) * 16 + c;
     double s = 0.0;
-    int c = 0;
-    for (; c + BATCH <= nchunk; c += BATCH) {
-        double v[BATCH];
+    if (i < ncoef) {
+        constexpr int BATCH = 8;
+        int k = sl;
+        for (; k + 16 * (BATCH - 1) < nchunk; k += 16 * BATCH) {
+            double v[BATCH];
 #pragma unroll
-        for (int k = 0; k < BATCH; ++k) v[k] = part[int64_t(c + k) * ncoef + i];
+            for (int u = 0; u < BATCH; ++u) v[u] = part[int64_t(k + 16 * u) * ncoef + i];
 #pragma unroll
-        for (int k = 0; k < BATCH; ++k) s += v[k];
+            for (int u = 0; u < BATCH; ++u) s += v[u];
+        }
+        for (; k < nchunk; k += 16) s += part[int64_t(k) * ncoef + i];
     }
-    for (; c < nchunk; ++c) s += part[int64_t(c) * ncoef + i];
-    out[i] = s;
+    sh[sl][c] = s;
+    __syncthreads();
+    if (sl == 0 && i < ncoef) {
+        double r = 0.0;
+        for (int q = 0; q < 16; ++q) r += sh[q][c];
+        out[i] = r;
+    }
 }
 
 // MODE 0: W[r][c] -= sum_q sum_k Q_q[r][k] C[q][k][c]
@@ -494,7 +505,9 @@ struct TsCtx {
     BlWork* W;
 };
 
-int chunks_for(int nq) { return std::max(16, std::min(256, 2048 / std::max(1, nq))); }
+// row chunks of a block inner product: up to 768 (three workgroups per CU of
+// 256), at most 2048 partial blocks over the nq blocks
+int chunks_for(int nq) { return std::max(16, std::min(768, 2048 / std::max(1, nq))); }
 
 // C[q][k][c] = sum_r Q_q[r][k] X[r][c] for q < nq  (C: nq b x b FP64, device)
 void ts_dots(const TsCtx& c, const float* Q, int nq, const float* X, double* C) {
@@ -511,7 +524,7 @@ void ts_dots(const TsCtx& c, const float* Q, int nq, const float* X, double* C) 
         default: throw Error(TBH_EINVAL, "block size must be 16, 32 or 64");
     }
     const int64_t ncoef = int64_t(nq) * c.b * c.b;
-    hipLaunchKernelGGL(k_ts_reduce, dim3(grid1(ncoef)), dim3(TPB), 0, c.st, nch, ncoef, part, C);
+    hipLaunchKernelGGL(k_ts_reduce, dim3(unsigned((ncoef + 15) / 16)), dim3(TPB), 0, c.st, nch, ncoef, part, C);
 }
 
 // MODE 0: X -= sum_q Q_q C_q;  MODE 1: X = Q_0 C_0
@@ -849,17 +862,53 @@ void FsWork::ensure(int64_t dim, int b_) {
 
 namespace {
 
-// one multi-vector launch out = (H + shift) in, on a descriptor slot of W.mvdesc
-void mv_apply(Ham& h, BlWork& W, int slot, const float* in, float* out, double shift, int b, hipStream_t st) {
-    MvDesc d{h.mv_blocks.as<float>(), h.nbr_d.as<int32_t>(), h.has_pot ? h.pot_d.as<double>() : nullptr,
-             in, out, 0, h.n, shift};
-    TBH_HIP(hipMemcpyAsync(W.mvdesc.as<MvDesc>() + slot, &d, sizeof(d), hipMemcpyHostToDevice, st));
+// the fastest (grid, atom walk) for H.X of this H with b vectors: 4 to 32
+// one-wavefront workgroups per compute unit x the three walks, each timed
+// over 3 launches after one untimed launch (on the caller's buffers; the
+// product that follows overwrites the output)
+void tune_mv(Ham& h, BlWork& W, const MvDesc* dd, int b, hipStream_t st) {
     int dev = 0;
     TBH_HIP(hipGetDevice(&dev));
     int n_cu = 256;
     (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    const int grid = int(std::min<int64_t>(int64_t(n_cu) * 32, h.n));   // 32 wavefronts per CU hide the gathers
-    mv_launch(false, h.n_o, b, W.mvdesc.as<MvDesc>() + slot, 1, h.n, grid, 1, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TBH_HIP(hipEventCreate(&e0));
+    TBH_HIP(hipEventCreate(&e1));
+    float best = INFINITY;
+    int bg = int(std::min<int64_t>(int64_t(n_cu) * 32, h.n)), br = 1;
+    for (int mult : {4, 8, 12, 16, 32})
+        for (int remap = 0; remap <= 2; ++remap) {
+            const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(n_cu) * mult, h.n)));
+            mv_launch(false, h.n_o, b, dd, 1, h.n, grid, remap, st);
+            TBH_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 3; ++r) mv_launch(false, h.n_o, b, dd, 1, h.n, grid, remap, st);
+            TBH_HIP(hipEventRecord(e1, st));
+            TBH_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            TBH_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bg = grid;
+                br = remap;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    W.mv_key = h.mv_blocks.p;
+    W.mv_n = h.n;
+    W.mv_b = b;
+    W.mv_grid = bg;
+    W.mv_remap = br;
+}
+
+// one multi-vector launch out = (H + shift) in, on a descriptor slot of W.mvdesc
+void mv_apply(Ham& h, BlWork& W, int slot, const float* in, float* out, double shift, int b, hipStream_t st) {
+    MvDesc d{h.mv_blocks.as<float>(), h.nbr_d.as<int32_t>(), h.has_pot ? h.pot_d.as<double>() : nullptr,
+             in, out, 0, h.n, shift};
+    MvDesc* dd = W.mvdesc.as<MvDesc>() + slot;
+    TBH_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    if (W.mv_grid == 0 || W.mv_key != h.mv_blocks.p || W.mv_n != h.n || W.mv_b != b) tune_mv(h, W, dd, b, st);
+    mv_launch(false, h.n_o, b, dd, 1, h.n, W.mv_grid, W.mv_remap, st);
 }
 
 }  // namespace

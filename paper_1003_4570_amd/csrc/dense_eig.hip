@@ -6,8 +6,8 @@
 //     Q = H_0 H_1 ... H_{n-2}, H_k = I - tau_k v_k v_k^T (one workgroup; the
 //     matrix, at most 2048^2 doubles, stays in L2);
 //  2. the eigenvalues of the tridiagonal nearest the target by Sturm-count
-//     bisection (one thread per eigenvalue, a window of 2 nc around the
-//     target's index);
+//     multisection (one wavefront per eigenvalue, a window of 2 nc around
+//     the target's index);
 //  3. their eigenvectors by inverse iteration with partial-pivot LU, from
 //     SplitMix64 start vectors that differ per candidate; candidates whose
 //     eigenvalues lie within 1e-8 |T| of each other (numerically degenerate,
@@ -199,9 +199,14 @@ __device__ void gersh(int n, const double* d, const double* e, double* lo, doubl
 }
 
 // eigenvalues with indices lo .. lo+cnt-1 (ascending), lo = clamp(count(sigma)
-// - nc, 0, n - cnt), cnt = min(2 nc, n); window[0..cnt-1], ctl[0] = lo
-__global__ void k_bisect_window(int n, const double* dg, const double* eg, double sigma, int nc, double* window,
-                                int* ctl) {
+// - nc, 0, n - cnt), cnt = min(2 nc, n); window[0..cnt-1], ctl[0] = lo.
+// One wavefront per eigenvalue, by multisection: lane l counts the
+// eigenvalues below the point l + 1 of 65 equal steps across the current
+// interval, which then shrinks to the step that holds the eigenvalue (six
+// bits per round where bisection gains one).  Stops, like bisection, at an
+// interval of 2 eps |x| or when the interval no longer shrinks.
+__global__ __launch_bounds__(64) void k_bisect_window(int n, const double* dg, const double* eg, double sigma,
+                                                      int nc, double* window, int* ctl) {
     // the tridiagonal, read by every Sturm count, staged in LDS
     __shared__ double d[MAXN], e[MAXN];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -209,29 +214,39 @@ __global__ void k_bisect_window(int n, const double* dg, const double* eg, doubl
         e[i] = i + 1 < n ? eg[i] : 0.0;
     }
     __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x;
     const int cnt = min(2 * nc, n);
     if (t >= cnt) return;
+    const int lane = threadIdx.x;
     double lo, hi, tn;
     gersh(n, d, e, &lo, &hi, &tn);
     const double eps = 2.220446049250313e-16;
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, tn * tn);
     const int i0 = sturm(n, d, e, sigma, pivmin);
     const int first = max(0, min(i0 - nc, n - cnt));
-    if (t == 0) ctl[0] = first;
+    if (t == 0 && lane == 0) ctl[0] = first;
     const int k = first + t;
     lo -= 2 * eps * tn + 1e-300;
     hi += 2 * eps * tn + 1e-300;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
+    for (int it = 0; it < 64; ++it) {
         if (hi - lo <= 2 * eps * fmax(fabs(lo), fabs(hi))) break;
-        if (sturm(n, d, e, mid, pivmin) >= k + 1)
-            hi = mid;
-        else
-            lo = mid;
+        const double w = hi - lo;
+        const double x = lo + w * double(lane + 1) / 65.0;
+        const unsigned long long above = __ballot(sturm(n, d, e, x, pivmin) >= k + 1);
+        double nlo, nhi;
+        if (above) {
+            const int j = __ffsll(above) - 1;   // first point with the eigenvalue below it
+            nhi = lo + w * double(j + 1) / 65.0;
+            nlo = j > 0 ? lo + w * double(j) / 65.0 : lo;
+        } else {
+            nlo = lo + w * 64.0 / 65.0;
+            nhi = hi;
+        }
+        if (!(nlo > lo || nhi < hi)) break;
+        lo = nlo;
+        hi = nhi;
     }
-    window[t] = 0.5 * (lo + hi);
+    if (lane == 0) window[t] = 0.5 * (lo + hi);
 }
 
 // the nc window values nearest sigma (ties: the lower value) form a
@@ -414,8 +429,8 @@ void symm_eig_near(hipStream_t st, int n, double* A, double sigma, int nc, EigWo
     else
         hipLaunchKernelGGL(k_sytrd, dim3(1), dim3(HT), 0, st, n, A, d, e, w.tau.as<double>(), w.V.as<double>());
     const int cnt = std::min(2 * nc, n);
-    hipLaunchKernelGGL(k_bisect_window, dim3((cnt + 63) / 64), dim3(64), 0, st, n, d, e, sigma, nc,
-                       w.window.as<double>(), w.ctl.as<int>());
+    hipLaunchKernelGGL(k_bisect_window, dim3(cnt), dim3(64), 0, st, n, d, e, sigma, nc, w.window.as<double>(),
+                       w.ctl.as<int>());
     hipLaunchKernelGGL(k_pick_window, dim3(1), dim3(64), 0, st, n, w.window.as<double>(), sigma, nc, theta);
     if (n <= SMALLN)
         hipLaunchKernelGGL(k_invit_lds, dim3((nc + IC - 1) / IC), dim3(IC), 0, st, n, d, e, theta, nc, S);

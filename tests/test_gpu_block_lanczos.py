@@ -30,9 +30,12 @@ def _nearest(ev, sigma, k):
     return np.sort(ev[idx])
 
 
-@pytest.mark.parametrize("n,nc,kind", [(37, 8, "random"), (256, 40, "random"), (700, 64, "clustered"),
-                                       (1024, 64, "clustered")])
+@pytest.mark.parametrize("n,nc,kind", [(37, 8, "random"), (64, 64, "random"), (48, 20, "clustered"),
+                                       (256, 40, "random"), (700, 64, "clustered"), (1024, 64, "clustered")])
 def test_projected_eigensolver_matches_lapack(ctx, n, nc, kind):
+    """n <= 64 takes the LDS kernels (one-wavefront reduction, interleaved
+    inverse iteration), as in the filtered solver's Rayleigh-Ritz (n = nc =
+    64); larger n the global-memory ones."""
     print(f"dense eig n={n} nc={nc} kind={kind}", flush=True)
     rng = np.random.default_rng(n)
     if kind == "random":
