@@ -592,15 +592,27 @@ void launch_sd(const Layout& lay, const HxArgs& h, hipStream_t s) {
 // 8-byte key record, the neighbour indices and the vectors, about 110 bytes
 // instead of 1.7 KB.  One atom per lane, one tile of 64 atoms per wavefront.
 // ---------------------------------------------------------------------------
+// LDS offset of table block `key`: 16 bytes of padding after every 8 blocks.
+// The keys that one bond slot takes across a wavefront differ by multiples
+// of 4 (the dense key order is sublattice, species, neighbour species,
+// slot), so unpadded 100-element blocks put all of them on two bank groups;
+// with the padding the 8 keys of a slot start on 8 different groups of 4
+// banks and stay 16-byte aligned.
+template <typename T, int NO>
+__host__ __device__ constexpr int tab_block_offset(int key) {
+    return key * NO * NO + (16 / int(sizeof(T))) * (key >> 3);
+}
+
 template <typename T, int NO, bool LZ>
 __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int ns) {
     extern __shared__ __align__(16) unsigned char smem[];
     T* tab = reinterpret_cast<T*>(smem);
     constexpr int ROWB = NO * sizeof(T);
     constexpr int BB = NO * NO;
-    const int nf = nu * BB + ns * NO;
     const T* __restrict__ gt = static_cast<const T*>(a.blocks);
-    for (int i = threadIdx.x; i < nf; i += blockDim.x) tab[i] = gt[i];
+    for (int i = threadIdx.x; i < nu * BB; i += blockDim.x) tab[tab_block_offset<T, NO>(i / BB) + i % BB] = gt[i];
+    const int d0 = tab_block_offset<T, NO>(nu);   // the on-site diagonals follow the last block
+    for (int i = threadIdx.x; i < ns * NO; i += blockDim.x) tab[d0 + i] = gt[nu * BB + i];
     __syncthreads();
 
     // Each XCD owns a contiguous share of the units of HX_WPB tiles, in
@@ -630,14 +642,14 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
         const int sp = int(kr.y & 0xffu);
         const T u_at = a.pot ? T(a.pot[atom]) : T(0);
         T acc[NO];
-        const T* __restrict__ dg = tab + nu * BB + sp * NO;
+        const T* __restrict__ dg = tab + d0 + sp * NO;
 #pragma unroll
         for (int r = 0; r < NO; ++r) acc[r] = (dg[r] + u_at) * xo[r];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const unsigned key = (kr.x >> (8 * b)) & 0xffu;
             if (key == 255u) continue;   // dangling bond
-            const T* __restrict__ B = tab + key * BB;
+            const T* __restrict__ B = tab + tab_block_offset<T, NO>(int(key));
 #pragma unroll
             for (int r = 0; r < NO; ++r)
 #pragma unroll
@@ -674,7 +686,9 @@ __global__ __launch_bounds__(64 * HX_WPB) void hx_tab_kernel(HxK a, int nu, int 
 }
 
 size_t tab_lds_bytes(const Layout& lay) {
-    return (size_t(lay.nu) * lay.n_o * lay.n_o + size_t(lay.ns) * lay.n_o) * size_t(lay.esz);
+    // the blocks with their padding (16 bytes per 8 blocks, as tab_block_offset), then the diagonals
+    return (size_t(lay.nu) * lay.n_o * lay.n_o + size_t(lay.ns) * lay.n_o) * size_t(lay.esz) +
+           16 * size_t(lay.nu >> 3);
 }
 
 template <typename T, int NO>
