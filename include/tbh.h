@@ -499,8 +499,10 @@ typedef struct {
      * from a random block) until the k_states pairs nearest the centre have
      * residual <= max(res_tol, 0.1 * the previous step's SCF residual) (0.01 *
      * with update_mode 1; max(res_tol, 0.01 eV) on the first step), at least
-     * one and at most filter_max_iter per step; every state of the block takes
-     * part in the filling. */
+     * one and at most filter_max_iter per step (see filter_max_iter_cold for the
+     * first); on a warm step with linear mixing the first filter's damping
+     * bound comes from the Ritz values the previous step ended with; every
+     * state of the block takes part in the filling. */
     int32_t eig_mode;
     int32_t block;            /* 16, 32 or 64 */
     int32_t filter_degree;
@@ -529,6 +531,14 @@ typedef struct {
     int32_t anderson_depth;   /* 0..8 */
     double newton_cg_tol;
     int32_t newton_cg_max_iter;
+    /* eig_mode 1 with linear mixing: at most this many filter passes in the
+     * loop's first (cold) eigen-solve, from the random block, when the start is
+     * the zero potential; 0 = filter_max_iter.  From the zero start the next
+     * steps' tolerance follows a large first residual, so that solve's
+     * accuracy is mostly unused; a built start (mean, learned, any potential
+     * set) and the Newton-Raphson update keep the full filter_max_iter
+     * (measured on the 8x8x60-cell slab). */
+    int32_t filter_max_iter_cold;
 } tbh_scf_opts;
 
 typedef struct {

@@ -103,7 +103,8 @@ class tbh_scf_opts(C.Structure):
                 ("filter_degree", C.c_int32), ("filter_degree_cold", C.c_int32), ("filter_max_iter", C.c_int32),
                 ("k_states", C.c_int32), ("e_vbm", C.c_double), ("update_mode", C.c_int32),
                 ("newton_states", C.c_int32), ("newton_kT", C.c_double), ("anderson_depth", C.c_int32),
-                ("newton_cg_tol", C.c_double), ("newton_cg_max_iter", C.c_int32)]
+                ("newton_cg_tol", C.c_double), ("newton_cg_max_iter", C.c_int32),
+                ("filter_max_iter_cold", C.c_int32)]
 
 
 class tbh_scf_report(C.Structure):
@@ -653,7 +654,7 @@ class SCF(_Handle):
                  cg_tol=1e-12, cg_max_iter=20000, fermi_fixed=None, eig_mode=0, block=64, filter_degree=20,
                  filter_degree_cold=60, filter_max_iter=20, k_states=40, e_vbm=float("nan"), update_mode=0,
                  newton_states=64, newton_kT=0.01, anderson_depth=4, newton_cg_tol=1e-6,
-                 newton_cg_max_iter=20000):
+                 newton_cg_max_iter=20000, filter_max_iter_cold=0):
         self._adopt(ham)
         self.ham = ham
         self.grid = tuple(int(g) for g in grid)
@@ -667,7 +668,8 @@ class SCF(_Handle):
                          self._v0.ctypes.data_as(C.POINTER(C.c_double)), int(eig_mode), int(block),
                          int(filter_degree), int(filter_degree_cold), int(filter_max_iter), int(k_states),
                          float(e_vbm), int(update_mode), int(newton_states), float(newton_kT),
-                         int(anderson_depth), float(newton_cg_tol), int(newton_cg_max_iter))
+                         int(anderson_depth), float(newton_cg_tol), int(newton_cg_max_iter),
+                         int(filter_max_iter_cold))
         h = C.c_void_p()
         _check(lib().tbh_scf_create(ham.h, C.byref(o), C.byref(h)))
         self.h = h

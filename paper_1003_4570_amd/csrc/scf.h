@@ -100,6 +100,7 @@ struct Scf {
     std::shared_ptr<FsWork> fs;
     bool fs_warm = false, have_bounds = false;
     bool fs_reuse = false;      // the block's last Ritz values describe the current start
+    bool zero_start = true;     // U was set to zero (construction or set_potential(NULL))
     DevBuf U_bounds;            // the potential the spectral bounds were taken at
     double emin_b = 0.0, emax_b = 0.0, last_res = 0.0;
     // Newton-Raphson update (update_mode 1)

@@ -502,8 +502,10 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     else
         TBH_REQUIRE((o.block == 16 || o.block == 32 || o.block == 64) && o.k_states >= 1 && o.k_states <= o.block &&
                         o.filter_degree >= 1 && o.filter_degree_cold >= 1 && o.filter_max_iter >= 1 &&
+                        o.filter_max_iter_cold >= 0 &&
                         h->has_mv && !h->cplx_h,
                     "filtered eigen-solve: block 16/32/64, 1 <= k_states <= block, degrees and filter_max_iter >= 1, "
+                    "filter_max_iter_cold >= 0, "
                     "and a real H built with multi_vector = 1");
     TBH_REQUIRE(o.update_mode == 0 || o.update_mode == 1, "update_mode must be 0 (linear mixing) or 1 (Newton)");
     if (o.update_mode == 1)
@@ -652,6 +654,7 @@ void Scf::set_start(const tbh_scf_start& sp) {
 void Scf::set_potential(const double* Ud) {
     hipStream_t st = h->ctx->stream;
     // null: the zero start; the loop's own buffer (a start built in place): kept as it is
+    zero_start = Ud == nullptr;
     if (!Ud)
         hipLaunchKernelGGL(k_scale, dim3(grid_for(n_nodes)), dim3(TPB), 0, st, n_nodes, U.as<double>(), 0.0,
                            U.as<double>());
@@ -757,7 +760,11 @@ void Scf::step(tbh_scf_report& rep) {
         so.degree = opt.filter_degree;
         so.degree_cold = opt.filter_degree_cold;
         so.min_iter = 1;
-        so.max_iter = opt.filter_max_iter;
+        // the first solve of a zero start under linear mixing needs little
+        // accuracy (the next steps' tolerance follows its large residual)
+        so.max_iter = (!fs_warm && zero_start && opt.update_mode == 0 && opt.filter_max_iter_cold > 0)
+                          ? opt.filter_max_iter_cold
+                          : opt.filter_max_iter;
         so.k = opt.k_states;
         // linear mixing moves U by a small fraction of the residual per step, so
         // early states need not be sharper than a tenth of it; a Newton step can
