@@ -901,14 +901,24 @@ void tune_mv(Ham& h, BlWork& W, const MvDesc* dd, int b, hipStream_t st) {
     W.mv_remap = br;
 }
 
-// one multi-vector launch out = (H + shift) in, on a descriptor slot of W.mvdesc
-void mv_apply(Ham& h, BlWork& W, int slot, const float* in, float* out, double shift, int b, hipStream_t st) {
-    MvDesc d{h.mv_blocks.as<float>(), h.nbr_d.as<int32_t>(), h.has_pot ? h.pot_d.as<double>() : nullptr,
-             in, out, 0, h.n, shift};
-    MvDesc* dd = W.mvdesc.as<MvDesc>() + slot;
-    TBH_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, st));
+MvDesc mv_desc(Ham& h, const float* in, float* out, double shift) {
+    return MvDesc{h.mv_blocks.as<float>(), h.nbr_d.as<int32_t>(), h.has_pot ? h.pot_d.as<double>() : nullptr,
+                  in, out, 0, h.n, shift};
+}
+
+// the multi-vector product of descriptor slot `slot` of W.mvdesc, in the
+// tuned launch shape
+void mv_run(Ham& h, BlWork& W, int slot, int b, hipStream_t st) {
+    const MvDesc* dd = W.mvdesc.as<MvDesc>() + slot;
     if (W.mv_grid == 0 || W.mv_key != h.mv_blocks.p || W.mv_n != h.n || W.mv_b != b) tune_mv(h, W, dd, b, st);
     mv_launch(false, h.n_o, b, dd, 1, h.n, W.mv_grid, W.mv_remap, st);
+}
+
+// one multi-vector launch out = (H + shift) in, its descriptor written to slot `slot`
+void mv_apply(Ham& h, BlWork& W, int slot, const float* in, float* out, double shift, int b, hipStream_t st) {
+    const MvDesc d = mv_desc(h, in, out, shift);
+    TBH_HIP(hipMemcpyAsync(W.mvdesc.as<MvDesc>() + slot, &d, sizeof(d), hipMemcpyHostToDevice, st));
+    mv_run(h, W, slot, b, st);
 }
 
 }  // namespace
@@ -919,40 +929,45 @@ void chfsi_filter(Ham& h, BlWork& W, FsWork& F, const FsOpts& o) {
     hipStream_t st = h.ctx->stream;
     const int b = F.b;
     const int64_t ne = h.dim * b;
-    W.mvdesc.alloc(sizeof(MvDesc) * 4);
     const double e = 0.5 * (o.fmax - o.fcut), c = 0.5 * (o.fmax + o.fcut);
     double sig = e / (c - o.fmin);
     const double tau = 2.0 / sig;
-    float* Y0 = F.Y.as<float>();
-    float* Y1 = F.Y0.as<float>();
-    float* Y2 = F.Y1.as<float>();
+    // the three blocks of the recurrence rotate; Y0, Y1, Y2 index them
+    float* blk[3] = {F.Y.as<float>(), F.Y0.as<float>(), F.Y1.as<float>()};
+    int Y0 = 0, Y1 = 1, Y2 = 2;
     float* T1 = F.T1.as<float>();
     float* FY = F.FY.as<float>();
+    // descriptors of the call, written once: slot r = (H - s) blk[r] -> T1,
+    // slot 3 = (H - s) T1 -> FY
+    W.mvdesc.alloc(sizeof(MvDesc) * 8);
+    const MvDesc ds[4] = {mv_desc(h, blk[0], T1, -o.s), mv_desc(h, blk[1], T1, -o.s), mv_desc(h, blk[2], T1, -o.s),
+                          mv_desc(h, T1, FY, -o.s)};
+    TBH_HIP(hipMemcpyAsync(W.mvdesc.p, ds, sizeof(ds), hipMemcpyHostToDevice, st));
     const dim3 g(unsigned((ne + TPB - 1) / TPB));
     // F Y = (H - s)((H - s) Y)
-    auto applyF = [&](const float* in) {
-        mv_apply(h, W, 0, in, T1, -o.s, b, st);
-        mv_apply(h, W, 1, T1, FY, -o.s, b, st);
+    auto applyF = [&](int in) {
+        mv_run(h, W, in, b, st);
+        mv_run(h, W, 3, b, st);
     };
     // Y1 = (F Y0 - c Y0) sig / e
     applyF(Y0);
-    hipLaunchKernelGGL(k_cheb_combine, g, dim3(TPB), 0, st, ne, FY, Y0, (const float*)nullptr, sig / e,
-                       -c * sig / e, 0.0, Y1);
+    hipLaunchKernelGGL(k_cheb_combine, g, dim3(TPB), 0, st, ne, FY, blk[Y0], (const float*)nullptr, sig / e,
+                       -c * sig / e, 0.0, blk[Y1]);
     for (int i = 2; i <= o.degree; ++i) {
         const double sig2 = 1.0 / (tau - sig);
         applyF(Y1);
         // Y2 = 2 sig2 / e (F Y1 - c Y1) - sig sig2 Y0
-        hipLaunchKernelGGL(k_cheb_combine, g, dim3(TPB), 0, st, ne, FY, Y1, Y0, 2.0 * sig2 / e,
-                           -2.0 * sig2 * c / e, -sig * sig2, Y2);
-        float* t = Y0;
+        hipLaunchKernelGGL(k_cheb_combine, g, dim3(TPB), 0, st, ne, FY, blk[Y1], blk[Y0], 2.0 * sig2 / e,
+                           -2.0 * sig2 * c / e, -sig * sig2, blk[Y2]);
+        const int t = Y0;
         Y0 = Y1;
         Y1 = Y2;
         Y2 = t;
         sig = sig2;
     }
     // the filtered block ends in Y1; keep it in F.Y
-    if (Y1 != F.Y.as<float>())
-        TBH_HIP(hipMemcpyAsync(F.Y.p, Y1, size_t(ne) * 4, hipMemcpyDeviceToDevice, st));
+    if (Y1 != 0)
+        TBH_HIP(hipMemcpyAsync(F.Y.p, blk[Y1], size_t(ne) * 4, hipMemcpyDeviceToDevice, st));
     TBH_HIP(hipGetLastError());
 }
 
@@ -970,12 +985,12 @@ void chfsi_rayleigh_ritz(Ham& h, BlWork& W, FsWork& F, bool states) {
     float* HY = F.T1.as<float>();
     float* Yr = F.Y.as<float>();
     float* HYr = F.FY.as<float>();
-    W.mvdesc.alloc(sizeof(MvDesc) * 4);
+    W.mvdesc.alloc(sizeof(MvDesc) * 8);
     TBH_HIP(hipMemsetAsync(W.ctl.p, 0, W.ctl.bytes, st));
     // orthonormal basis of the filtered block
     qr_block(c, F.Y.as<float>(), Yq, Bt, 0, 0, 1e-6, 1, small);
     // Rayleigh-Ritz of H on its span
-    mv_apply(h, W, 2, Yq, HY, 0.0, b, st);
+    mv_apply(h, W, 4, Yq, HY, 0.0, b, st);
     ts_dots(c, Yq, 1, HY, Ccoef);
     hipLaunchKernelGGL(k_sym_block, dim3(1), dim3(256), 0, st, b, Ccoef, Acoef, (const double*)nullptr,
                        W.ctl.as<double>());
