@@ -30,7 +30,7 @@ struct LzWork {
     std::vector<const void*> key;
     void drop_graph();
     ~LzWork();
-    void ensure(const Ham& h, int m, bool reorth, bool keep_basis);
+    void ensure(const Ham& h, int steps, bool with_reorth, bool keep_basis);
     LzDev dev(int m) const;
 };
 

@@ -516,27 +516,27 @@ int64_t grid_for(int64_t n) {
 // ---------------------------------------------------------------------------
 
 
-void LzWork::ensure(const Ham& h, int m, bool reorth, bool keep_basis) {
-    const bool want_full = reorth || keep_basis;
-    if (this->m == m && this->reorth == reorth && full == want_full && V.p && dim == h.dim) return;
+void LzWork::ensure(const Ham& h, int steps, bool with_reorth, bool keep_basis) {
+    const bool want_full = with_reorth || keep_basis;
+    if (m == steps && reorth == with_reorth && full == want_full && V.p && dim == h.dim) return;
     drop_graph();
     dim = h.dim;
     const int64_t ns = h.dim * (h.cplx_h ? 2 : 1);
     const size_t esz = h.prec == TBH_F64 ? 8 : 4;
-    TBH_REQUIRE(!reorth || m <= 4000, "full reorthogonalisation supports at most 4000 steps");
-    const int64_t nvec = want_full ? int64_t(m) + 1 : 3;
+    TBH_REQUIRE(!with_reorth || steps <= 4000, "full reorthogonalisation supports at most 4000 steps");
+    const int64_t nvec = want_full ? int64_t(steps) + 1 : 3;
     V.alloc(size_t(nvec) * ns * esz);
     w.alloc(size_t(ns) * esz);
-    scal.alloc(sizeof(double) * (2 * size_t(m) + 2 + LZ_NCTRL));
+    scal.alloc(sizeof(double) * (2 * size_t(steps) + 2 + LZ_NCTRL));
     const int64_t nblk_hx = hx_num_blocks(h.lay);
     const int64_t n_el = h.dim;
     const int64_t nrb = (n_el + 4 * TPB - 1) / (4 * TPB);
     size_t part_n = std::max<size_t>(2 * nblk_hx, 8192 * 3);
-    if (reorth) part_n = std::max<size_t>(part_n, size_t(m + 1) * nrb * 2);
+    if (with_reorth) part_n = std::max<size_t>(part_n, size_t(steps + 1) * nrb * 2);
     part.alloc(part_n * sizeof(double));
-    coef.alloc(sizeof(double) * 2 * (size_t(m) + 1));
-    this->m = m;
-    this->reorth = reorth;
+    coef.alloc(sizeof(double) * 2 * (size_t(steps) + 1));
+    m = steps;
+    reorth = with_reorth;
     full = want_full;
 }
 

@@ -431,14 +431,14 @@ __global__ void k_start_combine(int64_t n, const double* ubare, const float* mea
 // Poisson
 // ---------------------------------------------------------------------------
 
-void PoissonWork::ensure(int64_t n) {
-    if (this->n == n && r.p) return;
-    r.alloc(n * 8);
-    p.alloc(n * 8);
-    Ap.alloc(n * 8);
+void PoissonWork::ensure(int64_t nodes) {
+    if (n == nodes && r.p) return;
+    r.alloc(nodes * 8);
+    p.alloc(nodes * 8);
+    Ap.alloc(nodes * 8);
     part.alloc(2 * 4096 * 8);
     s.alloc(CG_NS * 8);
-    this->n = n;
+    n = nodes;
 }
 
 void poisson_cg_bufs(hipStream_t st, const PoissonBufs& W, const int grid[3], double h, const double* b,
@@ -523,9 +523,9 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
     TBH_REQUIRE(!h->pos_h.empty(), "ham has no positions");
     std::vector<char> seen(n_nodes, 0);
     auto node_of = [&](int64_t caller_atom) {
-        const int32_t* q = &h->pos_h[3 * caller_atom];
-        TBH_REQUIRE(q[0] < grid[0] && q[1] < grid[1] && q[2] < grid[2], "atom outside the Poisson grid");
-        return (int64_t(q[2]) * grid[1] + q[1]) * grid[0] + q[0];
+        const int32_t* pq = &h->pos_h[3 * caller_atom];
+        TBH_REQUIRE(pq[0] < grid[0] && pq[1] < grid[1] && pq[2] < grid[2], "atom outside the Poisson grid");
+        return (int64_t(pq[2]) * grid[1] + pq[1]) * grid[0] + pq[0];
     };
     for (int64_t i = 0; i < h->n; ++i) {
         node[i] = node_of(h->caller(i));
@@ -549,8 +549,8 @@ Scf::Scf(Ham* h_, const tbh_scf_opts& o) : h(h_), opt(o) {
         std::vector<float> dm(size_t(n_nodes), 0.f), mk(size_t(2 * n_nodes), 0.f);
         for (int d = 0; d < o.n_donors; ++d) dm[size_t(node_of(o.donor_atoms[d]))] += 1.f;
         for (int64_t a = 0; a < h->n; ++a) {
-            const int32_t* q = &h->pos_h[3 * a];
-            const bool bsub = (q[0] + q[1] + q[2]) % 4 == 3;
+            const int32_t* pq = &h->pos_h[3 * a];
+            const bool bsub = (pq[0] + pq[1] + pq[2]) % 4 == 3;
             mk[size_t((bsub ? n_nodes : 0) + node_of(a))] = 1.f;
         }
         dmap_d.alloc(size_t(n_nodes) * 4);
@@ -704,9 +704,9 @@ void Scf::step(tbh_scf_report& rep) {
         std::vector<double> ua(static_cast<size_t>(h->n));
         TBH_HIP(hipMemcpyAsync(ua.data(), Ua.p, ua.size() * 8, hipMemcpyDeviceToHost, st));
         TBH_HIP(hipStreamSynchronize(st));
-        const size_t q = size_t(0.01 * double(ua.size()));
-        std::nth_element(ua.begin(), ua.begin() + q, ua.end());
-        u_low = ua[q];
+        const size_t iq = size_t(0.01 * double(ua.size()));
+        std::nth_element(ua.begin(), ua.begin() + iq, ua.end());
+        u_low = ua[iq];
     }
     int steps = 0, ncand = 0;
     const double* Ys = nullptr;
